@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for Householder Dice -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this package.  The product library never calls it, and it
+imports nothing from the product package.
+
+``hd_oracle.c`` holds Algorithms 1 and 2 of Lu, "Householder Dice" (Sec. 3.2,
+Sec. 3.3) with reflectors applied one at a time; this module is the ctypes
+wrapper plus the dynamics maps f_t of eq. (dynamics) used by the workloads.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+GINIBRE = 0
+HAAR = 1
+SIDE_R = 0
+SIDE_L = 1
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        vp, i64, i32, u32, dbl = (ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int, ctypes.c_uint32,
+                                  ctypes.c_double)
+        L.hdo_new.restype = vp
+        L.hdo_new.argtypes = [i32, i64, i64, i32, u32, u32, dbl]
+        L.hdo_delete.argtypes = [vp]
+        L.hdo_delete.restype = None
+        L.hdo_query.argtypes = [vp, i32, vp, vp]
+        L.hdo_query.restype = i32
+        L.hdo_counts.argtypes = [vp, vp, vp, vp]
+        L.hdo_counts.restype = None
+        L.hdo_force_sign.argtypes = [vp, i32, i32, i32]
+        L.hdo_force_sign.restype = i32
+        L.hdo_reflector.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.hdo_reflector.restype = i32
+        L.hdo_basis.argtypes = [vp, i32, vp, vp]
+        L.hdo_basis.restype = i32
+        L.hdo_philox4x32_10.argtypes = [vp, vp, vp]
+        L.hdo_philox4x32_10.restype = None
+        L.hdo_normals.argtypes = [u32, u32, u32, u32, i64, i64, vp]
+        L.hdo_normals.restype = None
+        L.hdo_apply_householder.argtypes = [vp, i64, vp, vp, i32]
+        L.hdo_apply_householder.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block function (Salmon et al., SC'11)."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib().hdo_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normals(seed, trial, step, tag, i0, count):
+    """Normals i0..i0+count-1 of the stream (seed, trial, step, tag)."""
+    out = np.empty(int(count), dtype=np.float64)
+    if count:
+        lib().hdo_normals(seed, trial, step, tag, int(i0), int(count),
+                          _ptr(out))
+    return out
+
+
+def apply_householder(v, z, forced_sign=0):
+    """H(v) z with H of eq. (Householder); returns (result, is_identity)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty_like(z)
+    ident = lib().hdo_apply_householder(_ptr(v), v.size, _ptr(z), _ptr(out),
+                                        int(forced_sign))
+    if ident < 0:
+        raise MemoryError
+    return out, bool(ident)
+
+
+class HDOracle:
+    """Lazy random matrix Q (Ginibre GE(m,n) scaled by sigma, or Haar O(n))
+    answering y = Q x and y = Q' x by Algorithm 1 / Algorithm 2."""
+
+    def __init__(self, ensemble, n, m=None, tmax=None, seed=0, trial=0,
+                 sigma=1.0):
+        m = n if m is None else m
+        if tmax is None:
+            tmax = min(m, n)
+        self.ensemble, self.m, self.n, self.tmax = ensemble, m, n, tmax
+        self.seed, self.trial, self.sigma = seed, trial, sigma
+        self._h = lib().hdo_new(ensemble, m, n, tmax, seed, trial, sigma)
+        if not self._h:
+            raise ValueError("invalid oracle configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().hdo_delete(h)
+            self._h = None
+
+    def query(self, x, transpose=False):
+        din, dout = (self.m, self.n) if transpose else (self.n, self.m)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.shape != (din,):
+            raise ValueError("x has shape %s, expected (%d,)" % (x.shape, din))
+        y = np.empty(dout, dtype=np.float64)
+        rc = lib().hdo_query(self._h, int(bool(transpose)), _ptr(x), _ptr(y))
+        if rc == -2:
+            raise OverflowError("HD capacity exhausted")
+        if rc != 0:
+            raise MemoryError
+        return y
+
+    def mv(self, x):
+        return self.query(x, False)
+
+    def rmv(self, x):
+        return self.query(x, True)
+
+    def counts(self):
+        t, r, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lib().hdo_counts(self._h, ctypes.byref(t), ctypes.byref(r),
+                         ctypes.byref(l))
+        return t.value, r.value, l.value
+
+    def force_sign(self, side, index1, s):
+        if lib().hdo_force_sign(self._h, side, index1, int(s)) != 0:
+            raise IndexError(index1)
+
+    def reflector(self, side, index1):
+        """Reflector `index1` (1-based) of side SIDE_R / SIDE_L as a dict with
+        k, u (length dim-k+1), tau, s, nu, pivot, ident."""
+        dim = self.n if side == SIDE_R else self.m
+        u = np.zeros(dim - index1 + 1, dtype=np.float64)
+        tau, nu, piv = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        s, ident = ctypes.c_int(), ctypes.c_int()
+        rc = lib().hdo_reflector(self._h, side, index1, _ptr(u),
+                                 ctypes.byref(tau), ctypes.byref(s),
+                                 ctypes.byref(nu), ctypes.byref(piv),
+                                 ctypes.byref(ident))
+        if rc != 0:
+            raise IndexError(index1)
+        return dict(k=index1, u=u, tau=tau.value, s=s.value, nu=nu.value,
+                    pivot=piv.value, ident=bool(ident.value))
+
+    def basis(self, step1):
+        u = np.empty(self.m, dtype=np.float64)
+        v = np.empty(self.n, dtype=np.float64)
+        if lib().hdo_basis(self._h, step1, _ptr(u), _ptr(v)) != 0:
+            raise IndexError(step1)
+        return u, v
+
+
+# ---------------------------------------------------------------------
+# Dynamics maps f_t of eq. (dynamics) used by the workloads (FP64).
+# ---------------------------------------------------------------------
+
+def soft_threshold(v, theta):
+    """Element-wise soft threshold eta_theta(v) = sign(v) max(|v|-theta, 0)
+    (the operator in eq. (ista))."""
+    return np.sign(v) * np.maximum(np.abs(v) - theta, 0.0)
+
+
+def f_tanh_affine(y, x_t, x_prev, a, b):
+    """x_{t+1} = tanh(a y) + b x_t."""
+    return np.tanh(a * y) + b * x_t
+
+
+def f_soft_hist(y, x_t, x_prev, a, b):
+    """x_{t+1} = soft_threshold(y, a) + b x_{t-1}."""
+    return soft_threshold(y, a) + b * x_prev
+
+
+def f_normalize(y, x_t, x_prev, a, b):
+    """x_{t+1} = y / ||y|| + b x_t."""
+    return y / np.linalg.norm(y) + b * x_t
+
+
+DYNAMICS = {"tanh": f_tanh_affine, "soft_hist": f_soft_hist,
+            "normalize": f_normalize}
+
+
+def run_trajectory(orc, x1, T, dyn, a, b, pattern="Q", x0=None):
+    """Free-running trajectory (Mode A): returns X (T+1 rows: x_1..x_{T+1})
+    and Y (T rows).  pattern "Q" = every query uses Q, "alt" = Q, Q', Q, ..."""
+    f = DYNAMICS[dyn]
+    x_t = np.asarray(x1, dtype=np.float64)
+    x_prev = np.zeros_like(x_t) if x0 is None else np.asarray(x0, np.float64)
+    X, Y = [x_t.copy()], []
+    for t in range(T):
+        transpose = (pattern == "alt" and t % 2 == 1)
+        y = orc.query(x_t, transpose)
+        x_next = f(y, x_t, x_prev, a, b)
+        X.append(x_next)
+        Y.append(y)
+        x_prev, x_t = x_t, x_next
+    return np.array(X), np.array(Y)
+
+
+def replay(orc, xs, transposes):
+    """Mode B: answer the given query vectors in order; returns the outputs."""
+    return [orc.query(np.asarray(x, np.float64), bool(tr))
+            for x, tr in zip(xs, transposes)]

@@ -1,0 +1,26 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle_hd.so.
+
+Plain C11 with IEEE semantics (no fast-math, no -march) so the library built
+here runs on any x86-64 host.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hd_oracle.c")
+LIB = os.path.join(HERE, "liboracle_hd.so")
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", tmp, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

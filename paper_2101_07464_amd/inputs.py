@@ -1,0 +1,51 @@
+"""Seeded synthetic inputs for the Householder Dice workloads.
+
+This module only draws input vectors and workload shapes (initial conditions,
+sparse targets, noise, ragged batch sizes).  It contains none of the method's
+arithmetic: the random numbers that Householder Dice itself reveals are drawn
+inside the library (and, independently, inside the oracle) from the Philox
+stream keyed on (seed, trial).
+
+Every generator is numpy's PCG64 seeded with (seed, trial, tag); the tags keep
+the streams of different inputs apart.
+"""
+import numpy as np
+
+TAG_X1 = 1        # initial condition x_1
+TAG_SUPPORT = 2   # support of the sparse target x*
+TAG_AMPL = 3      # amplitudes of x*
+TAG_NOISE = 4     # observation noise
+TAG_BATCH = 5     # ragged batch shapes
+
+
+def rng(seed, trial, tag):
+    return np.random.default_rng(np.random.SeedSequence([seed, trial, tag]))
+
+
+def x1_normal(n, seed=0, trial=0, scale=None):
+    """x_1 ~ N(0, scale^2 I_n); scale defaults to 1/sqrt(n) (x_1 ~ N(0, I/n))."""
+    s = 1.0 / np.sqrt(n) if scale is None else scale
+    return rng(seed, trial, TAG_X1).standard_normal(n) * s
+
+
+def sparse_target(n, p_nonzero, sigma_s, seed=0, trial=0):
+    """Bernoulli-Gaussian vector: entry nonzero with probability p_nonzero,
+    nonzero entries N(0, sigma_s^2) (the prior of the lasso example)."""
+    sup = rng(seed, trial, TAG_SUPPORT).random(n) < p_nonzero
+    amp = rng(seed, trial, TAG_AMPL).standard_normal(n) * sigma_s
+    return np.where(sup, amp, 0.0)
+
+
+def noise(m, sigma_w, seed=0, trial=0):
+    return rng(seed, trial, TAG_NOISE).standard_normal(m) * sigma_w
+
+
+def ragged_batch(count, n_lo=1000, n_hi=100000, t_lo=10, t_hi=200, seed=0):
+    """Per-trial (n_b, T_b): n_b log-uniform in [n_lo, n_hi], T_b uniform in
+    [t_lo, t_hi]."""
+    g = rng(seed, 0, TAG_BATCH)
+    u = g.random(count)
+    n = np.floor(n_lo * (n_hi / n_lo) ** u).astype(np.int64)
+    n = np.clip(n, n_lo, n_hi)
+    T = g.integers(t_lo, t_hi + 1, size=count).astype(np.int64)
+    return n, T
