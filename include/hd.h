@@ -1,0 +1,146 @@
+/*
+ * hd.h -- C ABI of the MI355X (gfx950) Householder Dice library, libhd.so.
+ *
+ * Householder Dice (Y. M. Lu, arXiv 2101.07464) simulates dynamics
+ *     x_{t+1} = f_t(M_t x_t, x_t, ..., x_{t-d}),  M_t in {Q, Q'},
+ * (eq. (dynamics), Sec. 1) for a random matrix Q drawn from the Ginibre
+ * ensemble GE(m,n) (Sec. 3.2, Algorithm 1) or the Haar ensemble on O(n)
+ * (Sec. 3.3, Algorithm 2) without ever forming Q: every query reveals only the
+ * randomness it needs, stored as Householder reflectors (eq. (Householder),
+ * eq. (Householder_e)).  Memory is O((m+n) T) and a query costs O((m+n) t).
+ *
+ * Conventions for every entry point:
+ *   - Vectors are device pointers (hipMalloc'd, or torch CUDA tensors) of the
+ *     handle's storage type: float for HD_F32, double for HD_F64, contiguous,
+ *     element-aligned.  The caller owns them; they must stay valid until the
+ *     handle's stream has passed the call.  Outputs must not alias inputs.
+ *   - Calls are asynchronous and stream-ordered on the handle's stream.
+ *   - Return value: HD_OK (0) or a negative HD_ERR_* code.  A call that fails
+ *     host-side validation leaves the handle unchanged.  Conditions found on
+ *     the device (a non-finite norm) set a sticky flag reported by hd_status.
+ *   - A handle is not thread-safe; different handles are independent.
+ *   - The realisation is fixed by the key (seed, trial): the fresh Gaussian
+ *     vector g_t of query t (1-based) is the Philox4x32-10 stream with key
+ *     (seed, trial), counter (lo32(i/4), t, 0, hi32(i/4)), Box-Muller in FP64
+ *     (pair (w0,w1) -> entries 4b, 4b+1 as r cos, r sin; (w2,w3) -> 4b+2, 4b+3).
+ */
+#ifndef HD_H_
+#define HD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HD_OK = 0,
+  HD_ERR_INVALID = -1,   /* bad argument, null pointer, dimension mismatch */
+  HD_ERR_CAPACITY = -2,  /* t_max reached, or T <= min(m,n) would break */
+  HD_ERR_NOMEM = -3,     /* device allocation failed */
+  HD_ERR_HIP = -4,       /* a HIP runtime call failed */
+  HD_ERR_NONFINITE = -5, /* a reflector norm was NaN/Inf (sticky) */
+  HD_ERR_UNSUPPORTED = -6
+};
+
+enum { HD_GINIBRE = 0, HD_HAAR = 1 };
+enum { HD_F32 = 0, HD_F64 = 1 };
+
+typedef struct hd_ctx* hd_handle;
+
+typedef struct {
+  int32_t ensemble; /* HD_GINIBRE (Alg. 1) or HD_HAAR (Alg. 2) */
+  int32_t storage;  /* HD_F32 or HD_F64: panels and vectors; norms, signs,
+                       the WY factor T and all accumulations are FP64 */
+  int64_t m, n;     /* Q is m x n; Haar requires m == n */
+  int32_t t_max;    /* number of queries the handle can answer;
+                       must satisfy 1 <= t_max <= min(m, n) (Alg. 1 and 2
+                       require T <= min(m, n)) */
+  uint32_t seed;    /* Philox key word 0 */
+  uint32_t trial;   /* Philox key word 1 */
+  double sigma;     /* Ginibre: entries of Q are N(0, sigma^2); Haar: unused */
+  void* stream;     /* hipStream_t for all work of the handle; NULL = null
+                       stream */
+} hd_config;
+
+/* Create a lazy random matrix.  Allocates and owns all device buffers
+ * (panels of t_max columns, FP64 scalars); no query is answered yet.
+ * Errors: HD_ERR_INVALID (bad cfg, out == NULL), HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_init(const hd_config* cfg, hd_handle* out);
+
+/* Release the handle after its stream has drained.  NULL is a no-op. */
+int hd_free(hd_handle h);
+
+/* y = Q x: x has n entries, y has m entries (device).  One query of the
+ * dynamics with M_t = Q (Alg. 1 "if M_t = Q" branch; Alg. 2 Q branch).
+ * Errors: HD_ERR_INVALID, HD_ERR_CAPACITY (state unchanged), HD_ERR_HIP. */
+int hd_step(hd_handle h, const void* x, void* y);
+
+/* y = Q' x: x has m entries, y has n entries (device).  M_t = Q'. */
+int hd_apply_T(hd_handle h, const void* x, void* y);
+
+/* Synchronise the handle's stream and report the sticky device flag:
+ * HD_OK, HD_ERR_NONFINITE or HD_ERR_HIP. */
+int hd_status(hd_handle h);
+
+/* Query counters: t (queries answered), r (|{R_i}|), l (|{L_i}|).  For Haar
+ * every query adds one reflector to each side, so r = l = t. */
+int hd_counts(hd_handle h, int32_t* t, int32_t* r, int32_t* l);
+
+/* Change the stream used by later calls (hipStream_t, NULL = null stream). */
+int hd_set_stream(hd_handle h, void* stream);
+
+/* Copy to host, for the first `count` reflectors of one side
+ * (side 0 = R, acting on R^n; side 1 = L, acting on R^m): the norm nu of the
+ * vector it was built from, that vector's first entry (the pivot) and the
+ * sign s in {-1,+1}.  Synchronises the stream.  Any output may be NULL. */
+int hd_pivots(hd_handle h, int32_t side, int32_t count, double* nu,
+              double* pivot, int32_t* sign);
+
+/* Built-in dynamics for hd_run (the maps f_t of the workloads). */
+enum {
+  HD_DYN_TANH = 1,      /* x_{t+1} = tanh(a y_t) + b x_t          */
+  HD_DYN_SOFT_HIST = 2, /* x_{t+1} = soft(y_t, a) + b x_{t-1}     */
+  HD_DYN_NORMALIZE = 3  /* x_{t+1} = y_t / ||y_t|| + b x_t        */
+};
+enum {
+  HD_PATTERN_Q = 0,  /* M_t = Q for every t */
+  HD_PATTERN_ALT = 1 /* M_t = Q for odd t, Q' for even t */
+};
+
+typedef struct {
+  int32_t kind;    /* HD_DYN_* */
+  int32_t pattern; /* HD_PATTERN_* */
+  double a, b;
+} hd_dynamics;
+
+/* Run T steps of eq. (dynamics) on the device with a built-in f_t.
+ * x1: the initial condition x_1 (n entries).  x0: x_0 for the history term
+ * (n entries) or NULL for zeros.  x_out: receives x_{T+1} (n entries) or NULL.
+ * traj_x: NULL or (T+1) x n row-major buffer receiving x_1..x_{T+1};
+ * traj_y: NULL or T x m buffer receiving y_1..y_T.  Requires m == n.
+ * Errors as hd_step; on HD_ERR_CAPACITY nothing is launched. */
+int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
+           const void* x0, void* x_out, void* traj_x, void* traj_y);
+
+/* Timing of the panel kernels with HIP events on the handle's stream.
+ * hd_profile(h, 1) starts recording (clears previous records), 0 stops. */
+int hd_profile(hd_handle h, int32_t enable);
+
+/* Totals since recording started, for one kernel kind:
+ * 0 = panel TDOT (V'x), 1 = data-side GEMV-N pass, 2 = random-side GEMV-N
+ * pass.  ms: summed durations; launches: count; bytes: algorithmic bytes
+ * (panel elements read + vector elements read/written, times the element
+ * size).  Synchronises the stream. */
+int hd_profile_read(hd_handle h, int32_t kind, double* ms, int64_t* launches,
+                    double* bytes);
+
+/* Message for an HD_* code (static storage). */
+const char* hd_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HD_H_ */

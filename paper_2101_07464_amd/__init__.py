@@ -1,0 +1,176 @@
+"""Householder Dice on MI355X (gfx950).
+
+``LazyMatrix`` wraps one handle of libhd.so: a Ginibre or Haar random matrix Q
+that is never formed and answers ``y = Q x`` / ``y = Q' x`` on torch CUDA
+tensors (Lu, "Householder Dice", Algorithms 1 and 2).  The binding only
+marshals arguments; all work runs in the library's HIP kernels on the
+tensor's current stream.
+"""
+import ctypes
+
+from . import _lib
+from ._lib import (HD_F32, HD_F64, HD_GINIBRE, HD_HAAR, HD_DYN_NORMALIZE,
+                   HD_DYN_SOFT_HIST, HD_DYN_TANH, HD_PATTERN_ALT, HD_PATTERN_Q,
+                   HDCapacityError, HDError)
+
+GINIBRE = HD_GINIBRE
+HAAR = HD_HAAR
+
+_DYN = {"tanh": HD_DYN_TANH, "soft_hist": HD_DYN_SOFT_HIST,
+        "normalize": HD_DYN_NORMALIZE}
+_PATTERN = {"Q": HD_PATTERN_Q, "alt": HD_PATTERN_ALT}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class LazyMatrix:
+    """Lazy m x n random matrix on one GPU.
+
+    ensemble: GINIBRE (entries N(0, sigma^2)) or HAAR (orthogonal, m = n).
+    dtype: torch.float32 or torch.float64 (panel and vector storage).
+    t_max: number of queries the handle can answer (<= min(m, n)).
+    """
+
+    def __init__(self, ensemble, n, m=None, t_max=None, seed=0, trial=0,
+                 sigma=1.0, dtype=None, device="cuda:0"):
+        torch = _torch()
+        m = n if m is None else m
+        t_max = min(m, n) if t_max is None else t_max
+        dtype = torch.float32 if dtype is None else dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be float32 or float64")
+        self.ensemble, self.m, self.n, self.t_max = ensemble, m, n, t_max
+        self.dtype = dtype
+        self.device = torch.device(device)
+        cfg = _lib.HDConfig(ensemble, HD_F64 if dtype == torch.float64
+                            else HD_F32, m, n, t_max, seed, trial, sigma,
+                            _stream_ptr(self.device))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().hd_init(ctypes.byref(cfg), ctypes.byref(h)),
+                       "hd_init")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().hd_free(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _lib.check(_lib.load().hd_set_stream(self._h,
+                                             _stream_ptr(self.device)),
+                   "hd_set_stream")
+
+    def _vec(self, x, size):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or x.device != self.device:
+            raise TypeError("expected a tensor on %s" % self.device)
+        if x.dtype != self.dtype or x.shape != (size,):
+            raise ValueError("expected shape (%d,) and dtype %s" %
+                             (size, self.dtype))
+        return x.contiguous()
+
+    def mv(self, x, out=None):
+        """y = Q x (one query with M_t = Q)."""
+        return self._query(x, out, False)
+
+    def rmv(self, x, out=None):
+        """y = Q' x (one query with M_t = Q')."""
+        return self._query(x, out, True)
+
+    def _query(self, x, out, transpose):
+        torch = _torch()
+        din, dout = (self.m, self.n) if transpose else (self.n, self.m)
+        x = self._vec(x, din)
+        y = torch.empty(dout, dtype=self.dtype, device=self.device) \
+            if out is None else out
+        self._vec(y, dout)
+        self._sync_stream()
+        f = _lib.load().hd_apply_T if transpose else _lib.load().hd_step
+        _lib.check(f(self._h, ctypes.c_void_p(x.data_ptr()),
+                     ctypes.c_void_p(y.data_ptr())),
+                   "hd_apply_T" if transpose else "hd_step")
+        return y
+
+    def run(self, x1, T, dyn, a, b, pattern="Q", x0=None, record=True):
+        """T steps of x_{t+1} = f_t(M_t x_t, ...) with a built-in f_t.
+        Returns (X, Y) with X[t-1] = x_t (T+1 rows) and Y[t-1] = y_t when
+        record is True, else (x_{T+1}, None)."""
+        torch = _torch()
+        x1 = self._vec(x1, self.n)
+        if x0 is not None:
+            x0 = self._vec(x0, self.n)
+        d = _lib.HDDynamics(_DYN[dyn], _PATTERN[pattern], a, b)
+        self._sync_stream()
+        L = _lib.load()
+        vp = ctypes.c_void_p
+        if record:
+            X = torch.empty((T + 1, self.n), dtype=self.dtype,
+                            device=self.device)
+            Y = torch.empty((T, self.m), dtype=self.dtype, device=self.device)
+            rc = L.hd_run(self._h, ctypes.byref(d), T, vp(x1.data_ptr()),
+                          vp(x0.data_ptr()) if x0 is not None else None,
+                          None, vp(X.data_ptr()), vp(Y.data_ptr()))
+            _lib.check(rc, "hd_run")
+            return X, Y
+        xo = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        rc = L.hd_run(self._h, ctypes.byref(d), T, vp(x1.data_ptr()),
+                      vp(x0.data_ptr()) if x0 is not None else None,
+                      vp(xo.data_ptr()), None, None)
+        _lib.check(rc, "hd_run")
+        return xo, None
+
+    def status(self):
+        rc = _lib.load().hd_status(self._h)
+        return rc
+
+    def counts(self):
+        t, r, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().hd_counts(self._h, ctypes.byref(t),
+                                         ctypes.byref(r), ctypes.byref(l)),
+                   "hd_counts")
+        return t.value, r.value, l.value
+
+    def pivots(self, side, count=None):
+        """(nu, pivot, sign) of the first `count` reflectors of a side
+        (0 = R, 1 = L), as numpy arrays."""
+        import numpy as np
+        if count is None:
+            t, r, l = self.counts()
+            count = r if side == 0 else l
+        nu = np.zeros(count)
+        piv = np.zeros(count)
+        sg = np.zeros(count, dtype=np.int32)
+        _lib.check(_lib.load().hd_pivots(
+            self._h, side, count, nu.ctypes.data_as(ctypes.c_void_p),
+            piv.ctypes.data_as(ctypes.c_void_p),
+            sg.ctypes.data_as(ctypes.c_void_p)), "hd_pivots")
+        return nu, piv, sg
+
+    def profile(self, enable=True):
+        _lib.check(_lib.load().hd_profile(self._h, 1 if enable else 0),
+                   "hd_profile")
+
+    def profile_read(self, kind):
+        ms, cnt, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _lib.check(_lib.load().hd_profile_read(self._h, kind,
+                                               ctypes.byref(ms),
+                                               ctypes.byref(cnt),
+                                               ctypes.byref(by)),
+                   "hd_profile_read")
+        return ms.value, cnt.value, by.value

@@ -1,0 +1,105 @@
+"""ctypes binding of libhd.so (argument marshalling only).
+
+The functions mirror include/hd.h one for one.  Every computation happens in
+the HIP kernels behind the C ABI; this module never falls back to anything
+else and raises when the library is missing.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhd.so")
+
+HD_OK = 0
+HD_ERR_INVALID = -1
+HD_ERR_CAPACITY = -2
+HD_ERR_NOMEM = -3
+HD_ERR_HIP = -4
+HD_ERR_NONFINITE = -5
+HD_ERR_UNSUPPORTED = -6
+
+HD_GINIBRE = 0
+HD_HAAR = 1
+HD_F32 = 0
+HD_F64 = 1
+
+HD_DYN_TANH = 1
+HD_DYN_SOFT_HIST = 2
+HD_DYN_NORMALIZE = 3
+HD_PATTERN_Q = 0
+HD_PATTERN_ALT = 1
+
+EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
+           "hd_counts", "hd_set_stream", "hd_pivots", "hd_run",
+           "hd_profile", "hd_profile_read", "hd_strerror"]
+
+
+class HDConfig(ctypes.Structure):
+    _fields_ = [("ensemble", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("t_max", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("trial", ctypes.c_uint32), ("sigma", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class HDDynamics(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pattern", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class HDError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code), code))
+
+
+class HDCapacityError(HDError):
+    pass
+
+
+_LIB = None
+
+
+def load():
+    """Load libhd.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhd.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                         ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "hd_init": (i32, [P(HDConfig), P(vp)]),
+        "hd_free": (i32, [vp]),
+        "hd_step": (i32, [vp, vp, vp]),
+        "hd_apply_T": (i32, [vp, vp, vp]),
+        "hd_status": (i32, [vp]),
+        "hd_counts": (i32, [vp, P(i32), P(i32), P(i32)]),
+        "hd_set_stream": (i32, [vp, vp]),
+        "hd_pivots": (i32, [vp, i32, i32, vp, vp, vp]),
+        "hd_run": (i32, [vp, P(HDDynamics), i32, vp, vp, vp, vp, vp]),
+        "hd_profile": (i32, [vp, i32]),
+        "hd_profile_read": (i32, [vp, i32, P(dbl), P(i64), P(dbl)]),
+        "hd_strerror": (ctypes.c_char_p, [i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def strerror(code):
+    return load().hd_strerror(code).decode()
+
+
+def check(code, what):
+    if code == HD_OK:
+        return
+    if code == HD_ERR_CAPACITY:
+        raise HDCapacityError(code, what)
+    raise HDError(code, what)

@@ -1,0 +1,637 @@
+// hd_api.hip -- C-ABI runtime of libhd.so: handle state, validation, and the
+// per-query launch sequence.  All arithmetic runs in the kernels of
+// hd_kernels.hip; this file only orders launches on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hd.h"
+#include "hd_internal.hpp"
+
+using namespace hd;
+
+namespace {
+
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct hd_ctx {
+  hd_config cfg;
+  int f64;
+  int es;          // bytes per stored element
+  int64_t ld[2];   // leading dimension of side 0 (n) and side 1 (m)
+  int cpt[2];      // chunks per thread of the panel kernels, per side
+  int nwg[2];      // workgroups per panel pass, per side
+  int pstride, slot2, extra;
+  hipStream_t stream;
+  PanelDev P[2];   // 0 = R (acts on R^n), 1 = L (acts on R^m)
+  int pf_step[2];  // query index whose random-side prefetch P[s].red holds
+  int pending[2];  // data column whose T column still needs V'u, or -1
+  double* partials;
+  double* w;       // TDOT results (pstride)
+  double* zD;      // T' w (t_max)
+  double* zG;      // random-side coefficients + scratch (4 t_max)
+  double* head;    // rows < k of p (t_max)
+  double* scal;    // [0] pivot, [1] cscale
+  int* flag;
+  void* ring[3];   // internal trajectory vectors for hd_run
+  void* ybuf;
+  void* zeros;
+  int t, r, l;
+  std::vector<void*> allocs;
+  // profiling
+  int prof;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used;
+};
+
+namespace {
+
+thread_local char g_err[256];
+
+int hip_fail(hipError_t e) {
+  std::snprintf(g_err, sizeof(g_err), "%s", hipGetErrorString(e));
+  return HD_ERR_HIP;
+}
+
+#define HIPC(call)                               \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_);   \
+  } while (0)
+
+#define LCHK(call)                                              \
+  do {                                                          \
+    int e_ = (call);                                            \
+    if (e_ != 0) return hip_fail((hipError_t)(e_ > 0 ? e_ : 1)); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
+
+// Rows per workgroup = 1024 * cpt.  HD_CPT (1, 2, 4 or 8) overrides the
+// size-based choice, for tuning.
+int pick_cpt(int64_t n) {
+  const char* e = std::getenv("HD_CPT");
+  if (e) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+  }
+  if (n >= (int64_t)1 << 20) return 4;
+  if (n >= (int64_t)1 << 17) return 2;
+  return 1;
+}
+
+template <typename P>
+int dalloc(hd_ctx* h, P** out, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return HD_ERR_NOMEM;
+  }
+  h->allocs.push_back(p);
+  if (hipMemsetAsync(p, 0, bytes, h->stream) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  *out = (P*)p;
+  return HD_OK;
+}
+
+void free_all(hd_ctx* h) {
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  h->pool.clear();
+}
+
+// ------------------------------------------------------------ profiling --
+
+hipEvent_t prof_event(hd_ctx* h) {
+  if (h->pool_used == h->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->pool.push_back(e);
+  }
+  return h->pool[h->pool_used++];
+}
+
+struct ProfScope {
+  hd_ctx* h;
+  int kind;
+  double bytes;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hd_ctx* h_, int kind_, double bytes_)
+      : h(h_), kind(kind_), bytes(bytes_) {
+    if (h->prof) {
+      a = prof_event(h);
+      b = prof_event(h);
+      if (a && b) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (h->prof && a && b) {
+      (void)hipEventRecord(b, h->stream);
+      h->recs.push_back(ProfRec{kind, a, b, bytes});
+    }
+  }
+};
+
+// ---------------------------------------------------------- Haar query --
+
+SlotRanges ranges(int s0, int n0, int s1 = 0, int n1 = 0, int s2 = 0,
+                  int n2 = 0) {
+  SlotRanges r;
+  r.start[0] = s0;
+  r.count[0] = n0;
+  r.start[1] = s1;
+  r.count[1] = n1;
+  r.start[2] = s2;
+  r.count[2] = n2;
+  return r;
+}
+
+TdotArgs tdot_base(hd_ctx* h) {
+  TdotArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.partials = h->partials;
+  a.pstride = h->pstride;
+  a.slot2 = h->slot2;
+  a.extra = h->extra;
+  a.key = Key{h->cfg.seed, h->cfg.trial};
+  a.lo = -1;
+  return a;
+}
+
+PassArgs pass_base(hd_ctx* h, int side) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.V = h->P[side].V;
+  a.ld = h->ld[side];
+  a.pi = h->P[side].pi;
+  a.partials = h->partials;
+  a.pstride = h->pstride;
+  a.extra = h->extra;
+  a.key = Key{h->cfg.seed, h->cfg.trial};
+  return a;
+}
+
+// Prefetch of the random side for query `step` (1-based) on panel `side`
+// holding k columns: dots of its columns with g_step over rows > k and
+// ||g_step[k+1:]||^2, into P[side].red.
+int haar_prefetch(hd_ctx* h, int side, int k, int step) {
+  TdotArgs a = tdot_base(h);
+  a.V = h->P[side].V;
+  a.ld = h->ld[side];
+  a.ncols = k;
+  a.gen = 1;
+  a.gen_step = (uint32_t)step;
+  a.lo = k;
+  a.n = h->cfg.n;
+  a.want_ss = 1;
+  {
+    ProfScope ps(h, 0, (double)h->es * (double)h->ld[side] * k);
+    LCHK(launch_tdot(h->f64, h->cpt[side], a, h->nwg[side], h->stream));
+  }
+  LCHK(launch_reduce(h->partials, h->pstride, h->nwg[side],
+                     ranges(0, k, h->extra, kNumExtra), h->P[side].red,
+                     h->stream));
+  h->pf_step[side] = step;
+  return HD_OK;
+}
+
+const void* panel_col(hd_ctx* h, int side, int j) {
+  return (const char*)h->P[side].V + (size_t)h->es * (size_t)h->ld[side] * j;
+}
+
+// Complete the pending T column of a panel about to serve as the random
+// side: one pass of direct dots V[:, :k]' u_kp.
+int resolve_pending(hd_ctx* h, int side, int k) {
+  const int kp = h->pending[side];
+  if (kp < 0) return HD_OK;
+  if (kp > 0) {
+    TdotArgs a = tdot_base(h);
+    a.V = h->P[side].V;
+    a.ld = h->ld[side];
+    a.ncols = kp;
+    a.b = panel_col(h, side, kp);
+    a.n = side == 0 ? h->cfg.n : h->cfg.m;
+    {
+      ProfScope ps(h, 0, (double)h->es * (double)h->ld[side] * (kp + 1));
+      LCHK(launch_tdot(h->f64, h->cpt[side], a, h->nwg[side], h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[side],
+                       ranges(0, kp), h->w, h->stream));
+    SmallDataArgs sd;
+    sd.T = h->P[side].T;
+    sd.tau = h->P[side].tau;
+    sd.tmax = h->cfg.t_max;
+    sd.kp = kp;
+    sd.c = h->w;
+    sd.k = 0;
+    sd.w = nullptr;
+    sd.z = nullptr;
+    LCHK(launch_small_data(sd, h->stream));
+  }
+  (void)k;
+  h->pending[side] = -1;
+  return HD_OK;
+}
+
+int haar_query(hd_ctx* h, int transpose, const void* x, void* y,
+               int want_ysq) {
+  const int k = h->t;  // reflectors per side before this query
+  const int step = k + 1;
+  const int64_t n = h->cfg.n;
+  const int ds = transpose ? 1 : 0;  // data side
+  const int gs = 1 - ds;             // random side
+  if (h->pf_step[gs] != step) {
+    int rc = haar_prefetch(h, gs, k, step);
+    if (rc) return rc;
+  }
+  {
+    int rc = resolve_pending(h, gs, k);
+    if (rc) return rc;
+  }
+  const bool pf = step + 1 <= h->cfg.t_max;
+  const double es = (double)h->es;
+  // 1. w = V_D' x, together with V_D' u_kp for the pending column kp; then
+  //    T column kp and z_D = T_D' w
+  if (k > 0) {
+    const int kp = h->pending[ds];
+    TdotArgs a = tdot_base(h);
+    a.V = h->P[ds].V;
+    a.ld = h->ld[ds];
+    a.ncols = k;
+    a.b = x;
+    a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
+    a.n = n;
+    {
+      ProfScope ps(h, 0, es * ((double)h->ld[ds] * k + n +
+                               (kp > 0 ? (double)n : 0.0)));
+      LCHK(launch_tdot(h->f64, h->cpt[ds], a, h->nwg[ds], h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
+                       ranges(0, k, h->slot2, kp > 0 ? kp : 0), h->w,
+                       h->stream));
+    SmallDataArgs sd;
+    sd.T = h->P[ds].T;
+    sd.tau = h->P[ds].tau;
+    sd.tmax = h->cfg.t_max;
+    sd.kp = kp;
+    sd.c = h->w + h->slot2;
+    sd.k = k;
+    sd.w = h->w;
+    sd.z = h->zD;
+    LCHK(launch_small_data(sd, h->stream));
+    h->pending[ds] = -1;
+  }
+  // 2. p = Delta_D (x - V_D z_D); new column k of V_D; prefetch for step+1
+  {
+    PassArgs a = pass_base(h, ds);
+    a.k = k;
+    a.z = h->zD;
+    a.n = n;
+    a.x = x;
+    a.head = h->head;
+    a.pivot = h->scal;
+    a.pf = pf ? 1 : 0;
+    a.pf_step = (uint32_t)(step + 1);
+    a.pf_cut = k + 1;
+    {
+      ProfScope ps(h, 1, es * ((double)h->ld[ds] * k + n + (n - k)));
+      LCHK(launch_pass(h->f64, h->cpt[ds], kPassData, a, h->nwg[ds],
+                       h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
+                       ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                       h->P[ds].red, h->stream));
+  }
+  // 3. scalars of R_t and L_t, T/Gram columns, coefficients of the output
+  {
+    HaarSmallArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.D = h->P[ds];
+    a.G = h->P[gs];
+    a.k = k;
+    a.tmax = h->cfg.t_max;
+    a.storage_f64 = h->f64;
+    a.zG = h->zG;
+    a.head = h->head;
+    a.pivot = h->scal;
+    a.cscale = h->scal + 1;
+    a.key = Key{h->cfg.seed, h->cfg.trial};
+    a.step = (uint32_t)step;
+    a.extra = h->extra;
+    a.flag = h->flag;
+    LCHK(launch_haar_small(h->f64, a, h->stream));
+  }
+  // 4. y = (I - V_G T_G V_G') Delta_G w, w = [p[:k]; (nu/nu_G) g[k:]]
+  {
+    PassArgs a = pass_base(h, gs);
+    a.k = k;
+    a.z = h->zG;
+    a.n = n;
+    a.head = h->head;
+    a.cscale = h->scal + 1;
+    a.y = y;
+    a.step = (uint32_t)step;
+    a.want_ysq = want_ysq;
+    a.pf = pf ? 1 : 0;
+    a.pf_step = (uint32_t)(step + 1);
+    a.pf_cut = k + 1;
+    {
+      ProfScope ps(h, 2, es * ((double)h->ld[gs] * k + n + (n - k)));
+      LCHK(launch_pass(h->f64, h->cpt[gs], kPassRandHaar, a, h->nwg[gs],
+                       h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs],
+                       ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                       h->P[gs].red, h->stream));
+  }
+  h->t = step;
+  h->r = step;
+  h->l = step;
+  h->pf_step[ds] = pf ? step + 1 : 0;
+  h->pf_step[gs] = pf ? step + 1 : 0;
+  h->pending[ds] = k;
+  return HD_OK;
+}
+
+int check_query(hd_ctx* h, int transpose, const void* x, const void* y) {
+  if (!h || !x || !y || x == y) return HD_ERR_INVALID;
+  if (h->cfg.ensemble != HD_HAAR) return HD_ERR_UNSUPPORTED;
+  (void)transpose;
+  if (h->t >= h->cfg.t_max) return HD_ERR_CAPACITY;
+  return HD_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI --
+
+extern "C" {
+
+const char* hd_strerror(int code) {
+  switch (code) {
+    case HD_OK: return "ok";
+    case HD_ERR_INVALID: return "invalid argument";
+    case HD_ERR_CAPACITY: return "capacity exhausted (t_max or min(m,n))";
+    case HD_ERR_NOMEM: return "device allocation failed";
+    case HD_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case HD_ERR_NONFINITE: return "non-finite reflector norm";
+    case HD_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+int hd_init(const hd_config* cfg, hd_handle* out) {
+  if (!cfg || !out) return HD_ERR_INVALID;
+  *out = nullptr;
+  if (cfg->ensemble != HD_GINIBRE && cfg->ensemble != HD_HAAR)
+    return HD_ERR_INVALID;
+  if (cfg->storage != HD_F32 && cfg->storage != HD_F64) return HD_ERR_INVALID;
+  if (cfg->m <= 0 || cfg->n <= 0 || cfg->t_max < 1) return HD_ERR_INVALID;
+  if (cfg->ensemble == HD_HAAR && cfg->m != cfg->n) return HD_ERR_INVALID;
+  const int64_t cap = cfg->m < cfg->n ? cfg->m : cfg->n;
+  if ((int64_t)cfg->t_max > cap) return HD_ERR_INVALID;
+  if (cfg->ensemble == HD_GINIBRE && !(cfg->sigma > 0.0))
+    return HD_ERR_INVALID;
+  if (cfg->ensemble == HD_GINIBRE) return HD_ERR_UNSUPPORTED;
+  if (cfg->n > ((int64_t)1 << 40)) return HD_ERR_NOMEM;
+
+  hd_ctx* h = new (std::nothrow) hd_ctx();
+  if (!h) return HD_ERR_NOMEM;
+  h->cfg = *cfg;
+  h->stream = (hipStream_t)cfg->stream;
+  h->f64 = cfg->storage == HD_F64;
+  h->es = h->f64 ? 8 : 4;
+  const int64_t dims[2] = {cfg->n, cfg->m};
+  const int tm = cfg->t_max;
+  h->slot2 = (cfg->ensemble == HD_GINIBRE ? 2 * tm : tm) + 1;
+  h->extra = h->slot2 + tm + 1;
+  h->pstride = h->extra + kNumExtra;
+  int maxwg = 1;
+  for (int s = 0; s < 2; ++s) {
+    h->ld[s] = round_up(dims[s], kChunk);
+    h->cpt[s] = pick_cpt(dims[s]);
+    const int64_t rb = (int64_t)kChunk * h->cpt[s];
+    h->nwg[s] = (int)((h->ld[s] + rb - 1) / rb);
+    if (h->nwg[s] > maxwg) maxwg = h->nwg[s];
+  }
+  int rc = HD_OK;
+#define ALLOC(ptr, bytes)                                   \
+  do {                                                      \
+    rc = dalloc(h, &(ptr), (bytes));                        \
+    if (rc != HD_OK) {                                      \
+      free_all(h);                                          \
+      delete h;                                             \
+      return rc;                                            \
+    }                                                       \
+  } while (0)
+  for (int s = 0; s < 2; ++s) {
+    PanelDev& P = h->P[s];
+    P.ld = h->ld[s];
+    ALLOC(P.V, (size_t)h->es * (size_t)h->ld[s] * (size_t)tm);
+    ALLOC(P.T, sizeof(double) * (size_t)tm * tm);
+    ALLOC(P.tau, sizeof(double) * tm);
+    ALLOC(P.nu, sizeof(double) * tm);
+    ALLOC(P.piv, sizeof(double) * tm);
+    ALLOC(P.sgn, sizeof(double) * tm);
+    ALLOC(P.pi, sizeof(double) * (tm + 1));
+    ALLOC(P.red, sizeof(double) * h->pstride);
+    h->pf_step[s] = 0;
+    h->pending[s] = -1;
+  }
+  ALLOC(h->partials, sizeof(double) * (size_t)maxwg * h->pstride);
+  ALLOC(h->w, sizeof(double) * h->pstride);
+  ALLOC(h->zD, sizeof(double) * tm);
+  ALLOC(h->zG, sizeof(double) * 3 * (size_t)tm);
+  ALLOC(h->head, sizeof(double) * tm);
+  ALLOC(h->scal, sizeof(double) * 8);
+  ALLOC(h->flag, sizeof(int) * 4);
+#undef ALLOC
+  for (int s = 0; s < 2; ++s) {
+    if (launch_fill(h->P[s].pi, 1.0, 1, h->stream) != 0) {
+      free_all(h);
+      delete h;
+      return HD_ERR_HIP;
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+    int e = hip_fail(hipGetLastError());
+    free_all(h);
+    delete h;
+    return e;
+  }
+  *out = h;
+  return HD_OK;
+}
+
+int hd_free(hd_handle h) {
+  if (!h) return HD_OK;
+  free_all(h);
+  delete h;
+  return HD_OK;
+}
+
+int hd_set_stream(hd_handle h, void* stream) {
+  if (!h) return HD_ERR_INVALID;
+  h->stream = (hipStream_t)stream;
+  return HD_OK;
+}
+
+int hd_step(hd_handle h, const void* x, void* y) {
+  int rc = check_query(h, 0, x, y);
+  if (rc) return rc;
+  return haar_query(h, 0, x, y, 0);
+}
+
+int hd_apply_T(hd_handle h, const void* x, void* y) {
+  int rc = check_query(h, 1, x, y);
+  if (rc) return rc;
+  return haar_query(h, 1, x, y, 0);
+}
+
+int hd_status(hd_handle h) {
+  if (!h) return HD_ERR_INVALID;
+  HIPC(hipStreamSynchronize(h->stream));
+  int flag = 0;
+  HIPC(hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost));
+  return flag ? HD_ERR_NONFINITE : HD_OK;
+}
+
+int hd_counts(hd_handle h, int32_t* t, int32_t* r, int32_t* l) {
+  if (!h) return HD_ERR_INVALID;
+  if (t) *t = h->t;
+  if (r) *r = h->r;
+  if (l) *l = h->l;
+  return HD_OK;
+}
+
+int hd_pivots(hd_handle h, int32_t side, int32_t count, double* nu,
+              double* pivot, int32_t* sign) {
+  if (!h || (side != 0 && side != 1) || count < 0) return HD_ERR_INVALID;
+  const int have = side == 0 ? h->r : h->l;
+  if (count > have) return HD_ERR_INVALID;
+  if (count == 0) return HD_OK;
+  HIPC(hipStreamSynchronize(h->stream));
+  const PanelDev& P = h->P[side];
+  if (nu)
+    HIPC(hipMemcpy(nu, P.nu, sizeof(double) * count, hipMemcpyDeviceToHost));
+  if (pivot)
+    HIPC(hipMemcpy(pivot, P.piv, sizeof(double) * count,
+                   hipMemcpyDeviceToHost));
+  if (sign) {
+    std::vector<double> s(count);
+    HIPC(hipMemcpy(s.data(), P.sgn, sizeof(double) * count,
+                   hipMemcpyDeviceToHost));
+    for (int i = 0; i < count; ++i) sign[i] = s[i] < 0 ? -1 : 1;
+  }
+  return HD_OK;
+}
+
+int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
+           const void* x0, void* x_out, void* traj_x, void* traj_y) {
+  if (!h || !dyn || !x1 || T < 0) return HD_ERR_INVALID;
+  if (h->cfg.ensemble != HD_HAAR) return HD_ERR_UNSUPPORTED;
+  if (h->cfg.m != h->cfg.n) return HD_ERR_INVALID;
+  if (dyn->kind < HD_DYN_TANH || dyn->kind > HD_DYN_NORMALIZE)
+    return HD_ERR_INVALID;
+  // The normalising map is switched off: its one run on the GPU ended in a
+  // memory-aperture fault whose cause has not been shown (host emulation of
+  // the same launches under AddressSanitizer is clean).  It stays off until
+  // that cause is found.
+  if (dyn->kind == HD_DYN_NORMALIZE) return HD_ERR_UNSUPPORTED;
+  if (dyn->pattern != HD_PATTERN_Q && dyn->pattern != HD_PATTERN_ALT)
+    return HD_ERR_INVALID;
+  if ((int64_t)h->t + T > h->cfg.t_max) return HD_ERR_CAPACITY;
+  const int64_t n = h->cfg.n;
+  const size_t vb = (size_t)h->es * (size_t)n;
+  if (!traj_x && !h->ring[0]) {
+    for (int i = 0; i < 3; ++i) {
+      int rc = dalloc(h, &h->ring[i], vb);
+      if (rc) return rc;
+    }
+  }
+  if (!traj_y && !h->ybuf) {
+    int rc = dalloc(h, &h->ybuf, vb);
+    if (rc) return rc;
+  }
+  if (!x0 && !h->zeros) {
+    int rc = dalloc(h, &h->zeros, vb);
+    if (rc) return rc;
+  }
+  auto xrow = [&](int t) -> void* {  // x_t, t = 1..T+1
+    if (traj_x) return (char*)traj_x + (size_t)(t - 1) * vb;
+    return h->ring[(t - 1) % 3];
+  };
+  const void* xprev0 = x0 ? x0 : h->zeros;
+  if (xrow(1) != x1)
+    HIPC(hipMemcpyAsync(xrow(1), x1, vb, hipMemcpyDeviceToDevice, h->stream));
+  for (int t = 1; t <= T; ++t) {
+    const int transpose = (dyn->pattern == HD_PATTERN_ALT && t % 2 == 0);
+    void* y = traj_y ? (char*)traj_y + (size_t)(t - 1) * vb : h->ybuf;
+    int rc = haar_query(h, transpose, xrow(t), y,
+                        dyn->kind == HD_DYN_NORMALIZE);
+    if (rc) return rc;
+    DynArgs d;
+    d.kind = dyn->kind;
+    d.a = dyn->a;
+    d.b = dyn->b;
+    d.y = y;
+    d.x = xrow(t);
+    d.xprev = t == 1 ? xprev0 : xrow(t - 1);
+    d.xnext = xrow(t + 1);
+    d.n = n;
+    d.ysq = h->P[transpose ? 0 : 1].red + h->extra + kSlotYSQ;
+    LCHK(launch_dyn(h->f64, d, h->stream));
+  }
+  if (x_out && T >= 0 && x_out != xrow(T + 1))
+    HIPC(hipMemcpyAsync(x_out, xrow(T + 1), vb, hipMemcpyDeviceToDevice,
+                        h->stream));
+  return HD_OK;
+}
+
+int hd_profile(hd_handle h, int32_t enable) {
+  if (!h) return HD_ERR_INVALID;
+  HIPC(hipStreamSynchronize(h->stream));
+  h->prof = enable ? 1 : 0;
+  if (enable) {
+    h->recs.clear();
+    h->pool_used = 0;
+  }
+  return HD_OK;
+}
+
+int hd_profile_read(hd_handle h, int32_t kind, double* ms, int64_t* launches,
+                    double* bytes) {
+  if (!h) return HD_ERR_INVALID;
+  HIPC(hipStreamSynchronize(h->stream));
+  double tot = 0.0, by = 0.0;
+  int64_t cnt = 0;
+  for (const ProfRec& r : h->recs) {
+    if (r.kind != kind) continue;
+    float e = 0.f;
+    HIPC(hipEventElapsedTime(&e, r.a, r.b));
+    tot += e;
+    by += r.bytes;
+    ++cnt;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = cnt;
+  if (bytes) *bytes = by;
+  return HD_OK;
+}
+
+}  // extern "C"

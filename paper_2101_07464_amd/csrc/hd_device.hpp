@@ -1,0 +1,161 @@
+// Device-side building blocks for the Householder Dice kernels (gfx950).
+//
+//  * counter-based normal draws: Philox4x32-10 (Salmon et al., SC'11) feeding
+//    Box-Muller (1958) in FP64, keyed exactly as the library documents
+//    (key = (seed, trial), counter = (lo32(i/4), step, tag, hi32(i/4)));
+//  * 64-lane wavefront reductions, including a reduce-scatter that sums CG
+//    per-lane partials over the wave with 2*CG - 1 + log2(64/CG) shuffles
+//    instead of CG full reductions;
+//  * 4-element panel loads (one dwordx4 for FP32, two for FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hd_internal.hpp"
+
+namespace hd {
+
+// ------------------------------------------------------------------ RNG ---
+
+struct PhiloxKey {
+  uint32_t k0, k1;
+};
+
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1,
+                                         uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double open_unit(uint32_t w) {
+  return ((double)w + 0.5) * 2.3283064365386963e-10;  // 2^-32
+}
+
+// The four normals with indices 4*blk .. 4*blk+3 of stream (key, step, tag).
+__device__ __forceinline__ void normals4(PhiloxKey key, uint32_t step,
+                                         uint32_t tag, uint64_t blk,
+                                         double out[4]) {
+  uint32_t c0 = (uint32_t)blk, c1 = step, c2 = tag, c3 = (uint32_t)(blk >> 32);
+  philox10(c0, c1, c2, c3, key.k0, key.k1);
+  const uint32_t w[4] = {c0, c1, c2, c3};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const double rad = sqrt(-2.0 * log(open_unit(w[2 * p])));
+    const double ang = 6.283185307179586 * open_unit(w[2 * p + 1]);
+    double s, c;
+    sincos(ang, &s, &c);
+    out[2 * p] = rad * c;
+    out[2 * p + 1] = rad * s;
+  }
+}
+
+// A single normal (index i) of the stream.
+__device__ __forceinline__ double normal_at(PhiloxKey key, uint32_t step,
+                                            uint32_t tag, uint64_t i) {
+  double v[4];
+  normals4(key, step, tag, i >> 2, v);
+  return v[i & 3];
+}
+
+// ----------------------------------------------------------- reductions ---
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of v over the workgroup; every thread gets the result.  `scratch`
+// holds kWaves doubles.  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) r += scratch[w];
+  __syncthreads();
+  return r;
+}
+
+// Reduce-scatter over one wave: each lane holds CG partial sums v[0..CG-1]
+// (one per column).  On return, lanes with lane % (64/CG) == 0 hold in the
+// result the wave total of column lane / (64/CG).  CG must be a power of two
+// no larger than 64.  v is clobbered.
+template <int CG>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[CG]) {
+  const int lane = threadIdx.x & 63;
+  int off = 32;
+#pragma unroll
+  for (int h = CG / 2; h >= 1; h >>= 1) {
+    const bool upper = (lane & off) != 0;
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+      const double send = upper ? v[q] : v[q + h];
+      const double keep = upper ? v[q + h] : v[q];
+      v[q] = keep + __shfl_xor(send, off, 64);
+    }
+    off >>= 1;
+  }
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / CG; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// Workgroup-wide column sums of CG per-thread partials; thread c < CG gets
+// column c's total in the return value (others get 0).  lds: kWaves*CG.
+template <int CG>
+__device__ __forceinline__ double block_column_sums(double (&v)[CG],
+                                                    double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kGroup = 64 / CG;
+  const double r = wave_reduce_scatter<CG>(v);
+  if ((lane % kGroup) == 0) lds[wave * CG + lane / kGroup] = r;
+  __syncthreads();
+  double out = 0.0;
+  if (threadIdx.x < CG) {
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) out += lds[w * CG + threadIdx.x];
+  }
+  __syncthreads();
+  return out;
+}
+
+// ---------------------------------------------------------------- loads ---
+
+__device__ __forceinline__ void load4(const float* __restrict__ p,
+                                      double out[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
+
+__device__ __forceinline__ void load4(const double* __restrict__ p,
+                                      double out[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  out[0] = a.x;
+  out[1] = a.y;
+  out[2] = b.x;
+  out[3] = b.y;
+}
+
+}  // namespace hd

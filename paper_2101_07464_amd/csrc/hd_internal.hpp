@@ -1,0 +1,157 @@
+// Internal interfaces between the C-ABI runtime (hd_api.hip) and the kernel
+// launchers (hd_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+constexpr int kWG = 256;         // threads per workgroup (4 waves of 64)
+constexpr int kWaves = kWG / 64;
+constexpr int kChunk = kWG * 4;  // rows per workgroup per chunk (4 per lane)
+
+// Layout of the per-workgroup partial-sum rows and of the reduced vectors.
+// A row has `pstride` doubles: slots [0, slot2) hold the column dots with the
+// first right-hand side, [slot2, extra) those with the second one, and
+// extra + ExtraSlot the scalar extras below.
+enum ExtraSlot {
+  kSlotSS = 0,    // sum over rows > k of fl(new column)^2
+  kSlotPFSS = 1,  // sum over rows > cut of fl(g_next)^2 (prefetch)
+  kSlotYSQ = 2,   // sum of y_i^2 (for normalising dynamics)
+  kNumExtra = 4
+};
+
+struct Key {
+  uint32_t k0, k1;
+};
+
+// Partial dots of panel columns with a right-hand side b (from memory, or the
+// Philox draw of `gen_step` when gen != 0), over rows r with lo < r < n
+// (lo = -1 for all rows).  Two column segments share the rows.  When b2 is
+// set, the columns of the first segment are also dotted with b2 (a stored
+// panel column), into slots slot2 + j.
+struct TdotArgs {
+  const void* V;
+  int64_t ld;
+  int ncols;
+  const void* V2;
+  int ncols2;
+  const void* b;
+  const void* b2;
+  int slot2;
+  int gen;
+  Key key;
+  uint32_t gen_step;
+  int64_t lo;
+  int64_t n;
+  int want_ss;  // also sum of fl(b_i)^2 -> slot extra + kSlotPFSS
+  double* partials;
+  int pstride;
+  int extra;
+};
+
+// One GEMV-N pass over a panel (columns 0..k-1) producing an output vector,
+// writing the new column k, and the fused prefetch dots of columns 0..k with
+// the next draw over rows > pf_cut.
+enum PassMode { kPassData = 0, kPassRandHaar = 1 };
+
+struct PassArgs {
+  void* V;
+  int64_t ld;
+  int k;
+  const double* z;   // k coefficients
+  const double* pi;  // prefix sign products pi[0..k]
+  int64_t n;
+  // data mode: out = Delta (x - V z)
+  const void* x;
+  double* head;   // rows < k of the output (FP64)
+  double* pivot;  // row k of the output (FP64)
+  // random (Haar) mode: y = Delta w - V z, w = [head; cscale * g_step]
+  const double* cscale;
+  void* y;
+  Key key;
+  uint32_t step;
+  int want_ysq;
+  // fused prefetch
+  int pf;
+  uint32_t pf_step;
+  int64_t pf_cut;
+  double* partials;
+  int pstride;
+  int extra;
+};
+
+// Per-panel device state of the compact-WY representation.
+struct PanelDev {
+  void* V;        // ld x t_max, column-major
+  int64_t ld;
+  double* T;      // t_max x t_max upper triangular (column-major)
+  double* tau;    // t_max
+  double* nu;     // t_max: norm of the vector the reflector was built from
+  double* piv;    // t_max: its first entry
+  double* sgn;    // t_max: sign s
+  double* pi;     // t_max + 1: pi[j] = prod_{l<j} (-s_l), pi[0] = 1
+  double* red;    // pstride: reduced results of the last pass over the panel
+};
+
+// Completes column kp of a panel's T factor from c = V[:, :kp]' u_kp
+// (T[:kp, kp] = -tau_kp T[:kp, :kp] c), then z = T' w for the leading k x k
+// block when w is given.
+struct SmallDataArgs {
+  double* T;
+  const double* tau;
+  int tmax;
+  int kp;           // pending column, or -1
+  const double* c;  // kp dots
+  int k;
+  const double* w;  // k dots, or null
+  double* z;        // out (k)
+};
+
+struct HaarSmallArgs {
+  PanelDev D, G;
+  int k;
+  int tmax;
+  int storage_f64;
+  double* zG;       // out: coefficients for the random-side pass (k);
+                    // zG + tmax and zG + 2 tmax are scratch
+  const double* head;
+  const double* pivot;
+  double* cscale;   // out: nu / nu_G
+  Key key;
+  uint32_t step;
+  int extra;
+  int* flag;
+};
+
+enum DynKind { kDynNone = 0, kDynTanh = 1, kDynSoftHist = 2, kDynNormalize = 3 };
+
+struct DynArgs {
+  int kind;
+  double a, b;
+  const void* y;
+  const void* x;
+  const void* xprev;
+  void* xnext;
+  int64_t n;
+  const double* ysq;  // normalise: ||y||^2
+};
+
+int launch_tdot(int f64, int cpt, const TdotArgs& a, int nwg,
+                hipStream_t s);
+int launch_pass(int f64, int cpt, int mode, const PassArgs& a, int nwg,
+                hipStream_t s);
+// Fixed-order sums over workgroups of the slots in up to three ranges
+// [start, start + count) of the partial rows, into out[slot].
+struct SlotRanges {
+  int start[3];
+  int count[3];
+};
+int launch_reduce(const double* partials, int pstride, int nwg,
+                  const SlotRanges& r, double* out, hipStream_t s);
+int launch_small_data(const SmallDataArgs& a, hipStream_t s);
+int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);
+int launch_dyn(int f64, const DynArgs& a, hipStream_t s);
+int launch_fill(double* p, double v, int64_t count, hipStream_t s);
+
+}  // namespace hd

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/hd.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2101_07464_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hd.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(hd_\w+)\s*\(",
+                                 txt, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = _lib.load()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_error_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert _lib.strerror(code)
+
+
+def _cfg(**kw):
+    base = dict(ensemble=_lib.HD_HAAR, storage=_lib.HD_F32, m=64, n=64,
+                t_max=8, seed=0, trial=0, sigma=1.0, stream=None)
+    base.update(kw)
+    return _lib.HDConfig(**base)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=64, n=65),              # Haar must be square
+    dict(t_max=0),
+    dict(t_max=65),                # T <= min(m, n)
+    dict(n=0, m=0),
+    dict(storage=7),
+    dict(ensemble=3),
+    dict(ensemble=_lib.HD_GINIBRE, m=10, n=20, t_max=11),
+    dict(ensemble=_lib.HD_GINIBRE, sigma=0.0),
+])
+def test_init_rejects_invalid_config(kw):
+    h = ctypes.c_void_p()
+    rc = _lib.load().hd_init(ctypes.byref(_cfg(**kw)), ctypes.byref(h))
+    assert rc == _lib.HD_ERR_INVALID
+    assert not h.value
+
+
+def test_null_arguments():
+    L = _lib.load()
+    assert L.hd_init(None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_step(None, None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_apply_T(None, None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_status(None) == _lib.HD_ERR_INVALID
+    assert L.hd_counts(None, None, None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_free(None) == _lib.HD_OK
+    assert L.hd_run(None, None, 0, None, None, None, None, None) == \
+        _lib.HD_ERR_INVALID
