@@ -88,6 +88,11 @@ int hd_status(hd_handle h);
  * every query adds one reflector to each side, so r = l = t. */
 int hd_counts(hd_handle h, int32_t* t, int32_t* r, int32_t* l);
 
+/* Forget every revealed reflector and restart at t = 0 with a new key
+ * (seed, trial), reusing the handle's device buffers: the next query is the
+ * first query of a fresh, independent Q.  Stream-ordered; no allocation. */
+int hd_reset(hd_handle h, uint32_t seed, uint32_t trial);
+
 /* Change the stream used by later calls (hipStream_t, NULL = null stream). */
 int hd_set_stream(hd_handle h, void* stream);
 

@@ -193,17 +193,25 @@ DYNAMICS = {"tanh": f_tanh_affine, "soft_hist": f_soft_hist,
             "normalize": f_normalize}
 
 
-def run_trajectory(orc, x1, T, dyn, a, b, pattern="Q", x0=None):
+def run_trajectory(orc, x1, T, dyn, a, b, pattern="Q", x0=None,
+                   state_dtype=None):
     """Free-running trajectory (Mode A): returns X (T+1 rows: x_1..x_{T+1})
-    and Y (T rows).  pattern "Q" = every query uses Q, "alt" = Q, Q', Q, ..."""
+    and Y (T rows).  pattern "Q" = every query uses Q, "alt" = Q, Q', Q, ...
+
+    state_dtype=np.float32 rounds y_t and x_{t+1} to that type after each
+    step (the queries stay FP64): the divergence of that run from the FP64
+    one measures how much the dynamics themselves amplify storage rounding,
+    independent of any implementation of the queries."""
     f = DYNAMICS[dyn]
-    x_t = np.asarray(x1, dtype=np.float64)
+    rnd = (lambda v: v) if state_dtype is None else \
+        (lambda v: np.asarray(v, state_dtype).astype(np.float64))
+    x_t = rnd(np.asarray(x1, dtype=np.float64))
     x_prev = np.zeros_like(x_t) if x0 is None else np.asarray(x0, np.float64)
     X, Y = [x_t.copy()], []
     for t in range(T):
         transpose = (pattern == "alt" and t % 2 == 1)
-        y = orc.query(x_t, transpose)
-        x_next = f(y, x_t, x_prev, a, b)
+        y = rnd(orc.query(x_t, transpose))
+        x_next = rnd(f(y, x_t, x_prev, a, b))
         X.append(x_next)
         Y.append(y)
         x_prev, x_t = x_t, x_next

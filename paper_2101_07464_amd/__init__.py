@@ -135,6 +135,10 @@ class LazyMatrix:
         _lib.check(rc, "hd_run")
         return xo, None
 
+    def reset(self, seed, trial=0):
+        """Restart with a fresh matrix keyed (seed, trial), same buffers."""
+        _lib.check(_lib.load().hd_reset(self._h, seed, trial), "hd_reset")
+
     def status(self):
         rc = _lib.load().hd_status(self._h)
         return rc

@@ -30,7 +30,7 @@ HD_PATTERN_Q = 0
 HD_PATTERN_ALT = 1
 
 EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
-           "hd_counts", "hd_set_stream", "hd_pivots", "hd_run",
+           "hd_counts", "hd_reset", "hd_set_stream", "hd_pivots", "hd_run",
            "hd_profile", "hd_profile_read", "hd_strerror"]
 
 
@@ -78,6 +78,7 @@ def load():
         "hd_apply_T": (i32, [vp, vp, vp]),
         "hd_status": (i32, [vp]),
         "hd_counts": (i32, [vp, P(i32), P(i32), P(i32)]),
+        "hd_reset": (i32, [vp, ctypes.c_uint32, ctypes.c_uint32]),
         "hd_set_stream": (i32, [vp, vp]),
         "hd_pivots": (i32, [vp, i32, i32, vp, vp, vp]),
         "hd_run": (i32, [vp, P(HDDynamics), i32, vp, vp, vp, vp, vp]),

@@ -43,6 +43,11 @@ struct hd_ctx {
   double* zG;      // random-side coefficients + scratch (4 t_max)
   double* head;    // rows < k of p (t_max)
   double* scal;    // [0] pivot, [1] cscale
+  double* gscal;   // Ginibre: [0] nu, [1] sigma
+  double* z2;      // Ginibre: second coefficient vector of the random side
+  void* B[2];      // Ginibre explicit basis vectors: B[0] (n rows) holds v_t
+                   // of Q'-queries, B[1] (m rows) u_t of Q-queries
+  int64_t dim[2];  // n, m
   int* flag;
   void* ring[3];   // internal trajectory vectors for hd_run
   void* ybuf;
@@ -368,12 +373,175 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y,
   return HD_OK;
 }
 
+// Algorithm 1 query.  Data side D (R for y = Q x, L for y = Q' x) gets a new
+// reflector from p = D_k..D_1 x; the random side G answers
+//   y = sigma sum_i (v_i' x) u_i
+// with the implicit basis vectors of G (reflector products applied to
+// coefficients h = B_D' x from the TDOT pass) and the explicit ones in B[G]
+// (coefficients = the head of p, because the data-type basis vectors are
+// R_1..R_j e_j), and stores the new explicit vector (L..L Z g or R..R Z g).
+int gin_query(hd_ctx* h, int transpose, const void* x, void* y) {
+  const int ds = transpose ? 1 : 0;
+  const int gs = 1 - ds;
+  const int kD = ds == 0 ? h->r : h->l;
+  const int kG = ds == 0 ? h->l : h->r;
+  const int step = h->t + 1;
+  const int64_t nD = h->dim[ds], nG = h->dim[gs];
+  const double es = (double)h->es;
+  {
+    int rc = resolve_pending(h, gs, kG);
+    if (rc) return rc;
+  }
+  if (kG > 0 && h->pf_step[gs] != step) {
+    TdotArgs a = tdot_base(h);
+    a.V = h->P[gs].V;
+    a.ld = h->ld[gs];
+    a.ncols = kG;
+    a.gen = 1;
+    a.gen_step = (uint32_t)step;
+    a.lo = kG - 1;
+    a.n = nG;
+    {
+      ProfScope ps(h, 0, es * (double)h->ld[gs] * kG);
+      LCHK(launch_tdot(h->f64, h->cpt[gs], a, h->nwg[gs], h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs], ranges(0, kG),
+                       h->P[gs].red, h->stream));
+  }
+  const bool pf = step + 1 <= h->cfg.t_max;
+  // 1. w = V_D' x (+ pending column dots), h = B_D' x
+  if (kD + kG > 0) {
+    const int kp = h->pending[ds];
+    TdotArgs a = tdot_base(h);
+    a.V = h->P[ds].V;
+    a.ld = h->ld[ds];
+    a.ncols = kD;
+    a.V2 = h->B[ds];
+    a.ncols2 = kG;
+    a.b = x;
+    a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
+    a.n = nD;
+    {
+      ProfScope ps(h, 0, es * ((double)h->ld[ds] * (kD + kG) + nD +
+                               (kp > 0 ? (double)nD : 0.0)));
+      LCHK(launch_tdot(h->f64, h->cpt[ds], a, h->nwg[ds], h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
+                       ranges(0, kD + kG, h->slot2, kp > 0 ? kp : 0), h->w,
+                       h->stream));
+  }
+  {
+    SmallDataArgs sd;
+    sd.T = h->P[ds].T;
+    sd.tau = h->P[ds].tau;
+    sd.tmax = h->cfg.t_max;
+    sd.kp = h->pending[ds];
+    sd.c = h->w + h->slot2;
+    sd.k = kD;
+    sd.w = kD > 0 ? h->w : nullptr;
+    sd.z = h->zD;
+    LCHK(launch_small_data(sd, h->stream));
+    h->pending[ds] = -1;
+  }
+  // 2. p = Delta_D (x - V_D z_D), new column kD of V_D, prefetch for G-use
+  {
+    PassArgs a = pass_base(h, ds);
+    a.k = kD;
+    a.z = h->zD;
+    a.n = nD;
+    a.x = x;
+    a.head = h->head;
+    a.pivot = h->scal;
+    a.pf = pf ? 1 : 0;
+    a.pf_step = (uint32_t)(step + 1);
+    a.pf_cut = kD;
+    {
+      ProfScope ps(h, 1, es * ((double)h->ld[ds] * kD + nD + (nD - kD)));
+      LCHK(launch_pass(h->f64, h->cpt[ds], kPassData, a, h->nwg[ds],
+                       h->stream));
+    }
+    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
+                       ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
+                       h->P[ds].red, h->stream));
+  }
+  // 3. scalars of the new reflector; coefficients of the random side
+  {
+    GinSmallArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.D = h->P[ds];
+    a.G = h->P[gs];
+    a.k = kD;
+    a.l = kG;
+    a.tmax = h->cfg.t_max;
+    a.h = h->w + kD;
+    a.z1 = h->zG;
+    a.z2 = h->z2;
+    a.head = h->head;
+    a.pivot = h->scal;
+    a.scal = h->gscal;
+    a.D_extra = h->extra;
+    a.flag = h->flag;
+    LCHK(launch_gin_small(h->f64, a, h->stream));
+  }
+  // 4. y and the new explicit basis vector
+  {
+    GinPassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.V = h->P[gs].V;
+    a.ld = h->ld[gs];
+    a.k = kG;
+    a.z1 = h->zG;
+    a.z2 = h->z2;
+    a.pi = h->P[gs].pi;
+    a.B = h->B[gs];
+    a.nb = kD;
+    a.c = h->head;
+    a.h = h->w + kD;
+    a.scal = h->gscal;
+    a.n = nG;
+    a.y = y;
+    a.key = Key{h->cfg.seed, h->cfg.trial};
+    a.step = (uint32_t)step;
+    a.pf = pf ? 1 : 0;
+    a.pf_step = (uint32_t)(step + 1);
+    a.pf_cut = kG - 1;
+    a.partials = h->partials;
+    a.pstride = h->pstride;
+    a.extra = h->extra;
+    {
+      ProfScope ps(h, 2, es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG));
+      LCHK(launch_gin_pass(h->f64, h->cpt[gs], a, h->nwg[gs], h->stream));
+    }
+    if (pf && kG > 0)
+      LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs], ranges(0, kG),
+                         h->P[gs].red, h->stream));
+  }
+  h->t = step;
+  if (ds == 0)
+    h->r = kD + 1;
+  else
+    h->l = kD + 1;
+  h->pending[ds] = kD;
+  h->pf_step[ds] = pf ? step + 1 : 0;
+  h->pf_step[gs] = pf ? step + 1 : 0;
+  return HD_OK;
+}
+
 int check_query(hd_ctx* h, int transpose, const void* x, const void* y) {
   if (!h || !x || !y || x == y) return HD_ERR_INVALID;
-  if (h->cfg.ensemble != HD_HAAR) return HD_ERR_UNSUPPORTED;
-  (void)transpose;
   if (h->t >= h->cfg.t_max) return HD_ERR_CAPACITY;
+  if (h->cfg.ensemble == HD_GINIBRE) {
+    // Algorithm 1 needs r <= n and l <= m
+    const int kD = transpose ? h->l : h->r;
+    if ((int64_t)kD >= h->dim[transpose ? 1 : 0]) return HD_ERR_CAPACITY;
+  }
   return HD_OK;
+}
+
+int query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq) {
+  if (h->cfg.ensemble == HD_HAAR)
+    return haar_query(h, transpose, x, y, want_ysq);
+  return gin_query(h, transpose, x, y);
 }
 
 }  // namespace
@@ -407,7 +575,6 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   if ((int64_t)cfg->t_max > cap) return HD_ERR_INVALID;
   if (cfg->ensemble == HD_GINIBRE && !(cfg->sigma > 0.0))
     return HD_ERR_INVALID;
-  if (cfg->ensemble == HD_GINIBRE) return HD_ERR_UNSUPPORTED;
   if (cfg->n > ((int64_t)1 << 40)) return HD_ERR_NOMEM;
 
   hd_ctx* h = new (std::nothrow) hd_ctx();
@@ -417,6 +584,8 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   h->f64 = cfg->storage == HD_F64;
   h->es = h->f64 ? 8 : 4;
   const int64_t dims[2] = {cfg->n, cfg->m};
+  h->dim[0] = cfg->n;
+  h->dim[1] = cfg->m;
   const int tm = cfg->t_max;
   h->slot2 = (cfg->ensemble == HD_GINIBRE ? 2 * tm : tm) + 1;
   h->extra = h->slot2 + tm + 1;
@@ -459,10 +628,18 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   ALLOC(h->zG, sizeof(double) * 3 * (size_t)tm);
   ALLOC(h->head, sizeof(double) * tm);
   ALLOC(h->scal, sizeof(double) * 8);
+  ALLOC(h->gscal, sizeof(double) * 8);
+  ALLOC(h->z2, sizeof(double) * (size_t)tm);
+  if (cfg->ensemble == HD_GINIBRE) {
+    for (int s = 0; s < 2; ++s)
+      ALLOC(h->B[s], (size_t)h->es * (size_t)h->ld[s] * (size_t)tm);
+  }
   ALLOC(h->flag, sizeof(int) * 4);
 #undef ALLOC
-  for (int s = 0; s < 2; ++s) {
-    if (launch_fill(h->P[s].pi, 1.0, 1, h->stream) != 0) {
+  for (int s = 0; s < 3; ++s) {
+    double* p = s < 2 ? h->P[s].pi : h->gscal + 1;
+    const double v = s < 2 ? 1.0 : cfg->sigma;
+    if (launch_fill(p, v, 1, h->stream) != 0) {
       free_all(h);
       delete h;
       return HD_ERR_HIP;
@@ -485,6 +662,21 @@ int hd_free(hd_handle h) {
   return HD_OK;
 }
 
+int hd_reset(hd_handle h, uint32_t seed, uint32_t trial) {
+  if (!h) return HD_ERR_INVALID;
+  // Panel entries above each column's diagonal are never written, so they
+  // are still zero; every other entry a query reads is rewritten before it
+  // is read.  Only the host-side counters and the key change.
+  h->cfg.seed = seed;
+  h->cfg.trial = trial;
+  h->t = h->r = h->l = 0;
+  for (int s = 0; s < 2; ++s) {
+    h->pf_step[s] = 0;
+    h->pending[s] = -1;
+  }
+  return HD_OK;
+}
+
 int hd_set_stream(hd_handle h, void* stream) {
   if (!h) return HD_ERR_INVALID;
   h->stream = (hipStream_t)stream;
@@ -494,13 +686,13 @@ int hd_set_stream(hd_handle h, void* stream) {
 int hd_step(hd_handle h, const void* x, void* y) {
   int rc = check_query(h, 0, x, y);
   if (rc) return rc;
-  return haar_query(h, 0, x, y, 0);
+  return query(h, 0, x, y, 0);
 }
 
 int hd_apply_T(hd_handle h, const void* x, void* y) {
   int rc = check_query(h, 1, x, y);
   if (rc) return rc;
-  return haar_query(h, 1, x, y, 0);
+  return query(h, 1, x, y, 0);
 }
 
 int hd_status(hd_handle h) {
@@ -544,7 +736,6 @@ int hd_pivots(hd_handle h, int32_t side, int32_t count, double* nu,
 int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
            const void* x0, void* x_out, void* traj_x, void* traj_y) {
   if (!h || !dyn || !x1 || T < 0) return HD_ERR_INVALID;
-  if (h->cfg.ensemble != HD_HAAR) return HD_ERR_UNSUPPORTED;
   if (h->cfg.m != h->cfg.n) return HD_ERR_INVALID;
   if (dyn->kind < HD_DYN_TANH || dyn->kind > HD_DYN_NORMALIZE)
     return HD_ERR_INVALID;
@@ -556,6 +747,13 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
   if (dyn->pattern != HD_PATTERN_Q && dyn->pattern != HD_PATTERN_ALT)
     return HD_ERR_INVALID;
   if ((int64_t)h->t + T > h->cfg.t_max) return HD_ERR_CAPACITY;
+  if (h->cfg.ensemble == HD_GINIBRE) {
+    int nq = 0;
+    for (int t = 1; t <= T; ++t)
+      nq += !(dyn->pattern == HD_PATTERN_ALT && t % 2 == 0);
+    if ((int64_t)h->r + nq > h->cfg.n || (int64_t)h->l + (T - nq) > h->cfg.m)
+      return HD_ERR_CAPACITY;
+  }
   const int64_t n = h->cfg.n;
   const size_t vb = (size_t)h->es * (size_t)n;
   if (!traj_x && !h->ring[0]) {
@@ -582,8 +780,7 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
   for (int t = 1; t <= T; ++t) {
     const int transpose = (dyn->pattern == HD_PATTERN_ALT && t % 2 == 0);
     void* y = traj_y ? (char*)traj_y + (size_t)(t - 1) * vb : h->ybuf;
-    int rc = haar_query(h, transpose, xrow(t), y,
-                        dyn->kind == HD_DYN_NORMALIZE);
+    int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE);
     if (rc) return rc;
     DynArgs d;
     d.kind = dyn->kind;

@@ -108,6 +108,54 @@ struct SmallDataArgs {
   double* z;        // out (k)
 };
 
+// Random-side pass of a Ginibre query (Algorithm 1).  With G the random side
+// (l = k reflectors in V, Delta = diag(pi[min(i+1,l)])) and g the draw:
+//   u   = Delta [0_l; g[l:]] - V z1                (new explicit basis vector)
+//   out = sigma (B c + Delta (h + nu [0_l; g[l:]]) - V z2)
+// where B holds nb explicit basis vectors with coefficients c (FP64), h
+// (length l) the coefficients of the implicit basis vectors.  u is written to
+// column nb of B.  Fused prefetch of V' g_next over rows > pf_cut.
+struct GinPassArgs {
+  void* V;
+  int64_t ld;
+  int k;
+  const double* z1;
+  const double* z2;
+  const double* pi;
+  void* B;
+  int nb;
+  const double* c;
+  const double* h;
+  const double* scal;  // [0] nu, [1] sigma
+  int64_t n;
+  void* y;
+  Key key;
+  uint32_t step;
+  int pf;
+  uint32_t pf_step;
+  int64_t pf_cut;
+  double* partials;
+  int pstride;
+  int extra;
+};
+
+// Scalars of the data-side reflector and the coefficients of the random side
+// of a Ginibre query (one workgroup).
+struct GinSmallArgs {
+  PanelDev D, G;
+  int k;            // data-side reflectors before this query
+  int l;            // random-side reflectors
+  int tmax;
+  const double* h;  // l coefficients of the implicit random-side basis
+  double* z1;       // out (l)
+  double* z2;       // out (l); z1 + tmax .. are scratch
+  const double* head;
+  const double* pivot;
+  double* scal;     // out: [0] nu, [1] sigma (set by the host)
+  int D_extra;      // offset of the extra slots in D.red
+  int* flag;
+};
+
 struct HaarSmallArgs {
   PanelDev D, G;
   int k;
@@ -151,6 +199,9 @@ int launch_reduce(const double* partials, int pstride, int nwg,
                   const SlotRanges& r, double* out, hipStream_t s);
 int launch_small_data(const SmallDataArgs& a, hipStream_t s);
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);
+int launch_gin_pass(int f64, int cpt, const GinPassArgs& a, int nwg,
+                    hipStream_t s);
+int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s);
 int launch_dyn(int f64, const DynArgs& a, hipStream_t s);
 int launch_fill(double* p, double v, int64_t count, hipStream_t s);
 

@@ -365,6 +365,172 @@ __global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
   }
 }
 
+// ------------------------------------------------- Ginibre random side --
+
+template <typename T, int CPT>
+__global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
+  __shared__ double lds[kWaves * kCG];
+  const int tid = threadIdx.x;
+  const int k = a.k, nb = a.nb;
+  const int64_t blk0 = (int64_t)blockIdx.x * (kChunk * CPT);
+  const T* __restrict__ V = (const T*)a.V;
+  T* __restrict__ B = (T*)a.B;
+  const PhiloxKey key{a.key.k0, a.key.k1};
+  double acc1[CPT][4], acc2[CPT][4], gn[CPT][4];
+  bool cvalid[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t row0 = blk0 + (int64_t)c * kChunk;
+    cvalid[c] = row0 < a.ld;
+    const int64_t i0 = row0 + 4 * tid;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.pf && cvalid[c] && i0 < a.n && i0 + 3 > a.pf_cut)
+      normals4(key, a.pf_step, 0u, (uint64_t)(i0 >> 2), g);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + e;
+      acc1[c][e] = 0.0;
+      acc2[c][e] = 0.0;
+      gn[c][e] = (a.pf && cvalid[c] && i > a.pf_cut && i < a.n)
+                     ? (double)(T)g[e]
+                     : 0.0;
+    }
+  }
+  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
+  // reflector panel: two GEMV-N (z1 -> new basis vector, z2 -> output) and
+  // the prefetch dots
+#pragma unroll 1
+  for (int j0 = 0; j0 < k; j0 += kCG) {
+    double za[kCG], zb[kCG], pacc[kCG];
+#pragma unroll
+    for (int jj = 0; jj < kCG; ++jj) {
+      const bool ok = j0 + jj < k;
+      za[jj] = ok ? a.z1[j0 + jj] : 0.0;
+      zb[jj] = ok ? a.z2[j0 + jj] : 0.0;
+      pacc[jj] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (!cvalid[c]) continue;
+      const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
+#pragma unroll
+      for (int jj = 0; jj < kCG; ++jj) {
+        const int j = min(j0 + jj, k - 1);
+        double v[4];
+        load4(V + (int64_t)j * a.ld + r, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc1[c][e] -= v[e] * za[jj];
+          acc2[c][e] -= v[e] * zb[jj];
+          pacc[jj] += v[e] * gn[c][e];
+        }
+      }
+    }
+    if (a.pf) {
+      const double s = block_column_sums<kCG>(pacc, lds);
+      if (tid < kCG && j0 + tid < k) out[j0 + tid] = s;
+    }
+  }
+  // explicit basis panel: + B c
+#pragma unroll 1
+  for (int j0 = 0; j0 < nb; j0 += kCG) {
+    double cv[kCG];
+#pragma unroll
+    for (int jj = 0; jj < kCG; ++jj)
+      cv[jj] = (j0 + jj < nb) ? a.c[j0 + jj] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (!cvalid[c]) continue;
+      const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
+#pragma unroll
+      for (int jj = 0; jj < kCG; ++jj) {
+        const int j = min(j0 + jj, nb - 1);
+        double v[4];
+        load4(B + (int64_t)j * a.ld + r, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc2[c][e] += v[e] * cv[jj];
+      }
+    }
+  }
+  const double nu = a.scal[0], sigma = a.scal[1];
+  const double pik = a.pi[k];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    if (!cvalid[c]) continue;
+    const int64_t i0 = blk0 + (int64_t)c * kChunk + 4 * tid;
+    double gt[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i0 < a.n && i0 + 3 >= k)
+      normals4(key, a.step, 0u, (uint64_t)(i0 >> 2), gt);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + e;
+      if (i >= a.n) continue;
+      const double sg = (i < k) ? a.pi[i + 1] : pik;
+      const double gi = (i >= k) ? gt[e] : 0.0;
+      B[(int64_t)nb * a.ld + i] = (T)(sg * gi + acc1[c][e]);
+      const double hv = (i < k) ? a.h[i] : 0.0;
+      ((T*)a.y)[i] = (T)(sigma * (acc2[c][e] + sg * (hv + nu * gi)));
+    }
+  }
+}
+
+// Data-side scalars (as for Haar) and the random-side coefficients of a
+// Ginibre query: s1 = V_G' Delta_G [0; g] = pi_l * (prefetched dots),
+// s2 = V_G' Delta_G h (head rows only) + nu s1; z1 = T_G s1, z2 = T_G s2.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_gin_small(GinSmallArgs a) {
+  __shared__ double sh[2];
+  const int k = a.k, l = a.l, tid = threadIdx.x, tm = a.tmax;
+  T* VD = (T*)a.D.V;
+  const T* VG = (const T*)a.G.V;
+  const int64_t ldD = a.D.ld, ldG = a.G.ld;
+  double* s1 = a.z1 + tm;
+  double* s2 = a.z1 + 2 * tm;
+  if (tid == 0) {
+    const double ss = a.D.red[a.D_extra + kSlotSS];
+    const double pk = *a.pivot;
+    const double nu = sqrt(ss + pk * pk);
+    double s = 1.0, tau = 0.0, up = 0.0;
+    if (nu > 0.0) {
+      s = pk >= 0.0 ? 1.0 : -1.0;
+      up = (double)(T)(pk + s * nu);
+      tau = 2.0 / (ss + up * up);
+    }
+    if (!isfinite(nu) || !isfinite(tau)) a.flag[0] = 1;
+    VD[(int64_t)k * ldD + k] = (T)up;
+    a.D.tau[k] = tau;
+    a.D.nu[k] = nu;
+    a.D.piv[k] = pk;
+    a.D.sgn[k] = s;
+    a.D.pi[k + 1] = nu > 0.0 ? a.D.pi[k] * (-s) : a.D.pi[k];
+    a.D.T[k + (int64_t)k * tm] = tau;
+    a.scal[0] = nu;
+    sh[0] = nu;
+  }
+  __syncthreads();
+  const double nu = sh[0];
+  const double pil = a.G.pi[l];
+  for (int j = tid; j < l; j += kWG) {
+    const T* col = VG + (int64_t)j * ldG;
+    double hs = 0.0;
+    for (int i = 0; i < l; ++i) hs += (double)col[i] * a.G.pi[i + 1] * a.h[i];
+    const double v1 = pil * a.G.red[j];
+    s1[j] = v1;
+    s2[j] = hs + nu * v1;
+  }
+  __syncthreads();
+  for (int j = tid; j < l; j += kWG) {
+    double z1 = 0.0, z2 = 0.0;
+    for (int q = j; q < l; ++q) {
+      const double tjq = a.G.T[j + (int64_t)q * tm];
+      z1 += tjq * s1[q];
+      z2 += tjq * s2[q];
+    }
+    a.z1[j] = z1;
+    a.z2[j] = z2;
+  }
+}
+
 // ------------------------------------------------------------- dynamics --
 
 template <typename T>
@@ -477,6 +643,35 @@ int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<double>), dim3(1), dim3(kWG), 0, s, a);
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<float>), dim3(1), dim3(kWG), 0, s, a);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+static int gin_pass_cpt(int cpt, const GinPassArgs& a, int nwg,
+                        hipStream_t s) {
+  switch (cpt) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 1>), dim3(nwg), dim3(kWG), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 2>), dim3(nwg), dim3(kWG), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4>), dim3(nwg), dim3(kWG), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 8>), dim3(nwg), dim3(kWG), 0, s, a); break;
+    default: return -1;
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_gin_pass(int f64, int cpt, const GinPassArgs& a, int nwg,
+                    hipStream_t s) {
+  return f64 ? gin_pass_cpt<double>(cpt, a, nwg, s)
+             : gin_pass_cpt<float>(cpt, a, nwg, s);
+}
+
+int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s) {
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<double>), dim3(1), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<float>), dim3(1), dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
 }
