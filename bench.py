@@ -1,0 +1,166 @@
+"""Benchmark of the Householder Dice step on one MI355X.
+
+A step is one whole trajectory of the workload: hd_reset (a fresh random
+matrix, new Philox key) followed by T queries of eq. (dynamics) with the
+workload's map f_t, all on the GPU, inputs resident in HBM.  The metric is
+nominal element updates per second, W = n * sum_{t<=T} t per trajectory
+(n the larger dimension), plus the roofline of the dominant panel kernel.
+
+Workloads (--workload):
+  c2  (default) Ginibre n = m = 65536, sigma = 1/sqrt(n), T = 100, queries
+      Q, Q', Q, ...; x_{t+1} = soft(y_t, 0.1) + 0.3 x_{t-1}, x_1 ~ N(0, I),
+      x_0 = 0; FP32 panels and vectors, FP64 accumulation, norms and T.
+  c1  Haar n = 1000, T = 20, FP64; x_{t+1} = tanh(y_t) + 0.5 x_t,
+      x_1 ~ N(0, I/n).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("HD n*t elem-updates/s and % HBM peak; batched/adjoint vs plain "
+          "at err<=1e-4")
+HBM_PEAK_GBS = 8000.0
+KIND_NAMES = {0: "panel TDOT (k_tdot)", 1: "data-side GEMV-N (k_pass)",
+              2: "random-side GEMV-N (k_pass / k_gin_pass)"}
+
+WORKLOADS = {
+    "c2": dict(name="ginibre_n65536_T100_alt_soft_fp32", ensemble="ginibre",
+               n=65536, T=100, dyn="soft_hist", a=0.1, b=0.3, pattern="alt",
+               f64=False, x1_scale=1.0),
+    "c1": dict(name="haar_n1000_T20_tanh_fp64", ensemble="haar", n=1000,
+               T=20, dyn="tanh", a=1.0, b=0.5, pattern="Q", f64=True,
+               x1_scale=None),
+}
+
+
+def nominal_work(n, T):
+    return n * T * (T + 1) / 2.0
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 oracle (single-threaded C) on the same workload: whole
+    trajectories while they fit the time budget, else the first queries of
+    one trajectory; elem-updates/s over what it finished."""
+    import oracle
+    from paper_2101_07464_amd import inputs
+    n, T = wl["n"], wl["T"]
+    ens = oracle.GINIBRE if wl["ensemble"] == "ginibre" else oracle.HAAR
+    sig = 1.0 / np.sqrt(n) if ens == oracle.GINIBRE else 1.0
+    f = oracle.DYNAMICS[wl["dyn"]]
+    x1 = inputs.x1_normal(n, seed=0, scale=wl["x1_scale"])
+    t0 = time.perf_counter()
+    work, done, trial = 0.0, 0, 0
+    while True:
+        orc = oracle.HDOracle(ens, n, tmax=T, seed=0, trial=trial, sigma=sig)
+        x, xp = x1.copy(), np.zeros(n)
+        for t in range(T):
+            tr = wl["pattern"] == "alt" and t % 2 == 1
+            y = orc.query(x, tr)
+            x, xp = f(y, x, xp, wl["a"], wl["b"]), x
+            work += n * (t + 1)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        trial += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=work / dt, unit="elem-updates/s", cores=1, kind="oracle",
+                sample="%d queries (%d trajectories started) of the same "
+                       "workload, FP64 C oracle, single thread, %.1f s"
+                       % (done, trial, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import inputs
+
+    wl = WORKLOADS[args.workload]
+    n, T = wl["n"], wl["T"]
+    dev = "cuda:0"
+    dtype = torch.float64 if wl["f64"] else torch.float32
+    ens = hd.GINIBRE if wl["ensemble"] == "ginibre" else hd.HAAR
+    sig = 1.0 / np.sqrt(n) if ens == hd.GINIBRE else 1.0
+    x1 = torch.from_numpy(inputs.x1_normal(n, seed=0, scale=wl["x1_scale"]))
+    x1 = x1.to(dev, dtype)
+    A = hd.LazyMatrix(ens, n, t_max=T, seed=0, sigma=sig, dtype=dtype,
+                      device=dev)
+
+    def step(i):
+        A.reset(0, i)
+        A.run(x1, T, wl["dyn"], wl["a"], wl["b"], wl["pattern"],
+              record=False)
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    A.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if A.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    kinds = {k: A.profile_read(k) for k in (0, 1, 2)}
+    A.profile(False)
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, launches, nbytes = kinds[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    W = nominal_work(n, T)
+    out = {
+        "metric": METRIC,
+        "value": W * args.steps / elapsed,
+        "unit": "elem-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl["f64"] else "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "T": T,
+                   "ensemble": wl["ensemble"], "pattern": wl["pattern"],
+                   "dynamics": wl["dyn"],
+                   "precision": ("FP64 panels and vectors" if wl["f64"] else
+                                 "FP32 panels and vectors, FP64 accumulation,"
+                                 " norms, signs and T"),
+                   "elem_updates_per_step": W},
+        "roofline": {"bound": "hbm", "kernel": KIND_NAMES[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": launches,
+                     "avg_launch_us": ms * 1e3 / max(launches, 1),
+                     "algorithmic_bytes_per_launch": nbytes / max(launches, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
