@@ -29,9 +29,10 @@ struct hd_ctx {
   hd_config cfg;
   int f64;
   int es;          // bytes per stored element
-  int64_t ld[2];   // leading dimension of side 0 (n) and side 1 (m)
-  int cpt[2];      // chunks per thread of the panel kernels, per side
-  int nwg[2];      // workgroups per panel pass, per side
+  int64_t dim[2];  // n (side 0, R), m (side 1, L)
+  int64_t ld[2];   // leading dimension of the panels of each side
+  Shape sh[2];     // launch shape of the panel kernels of each side
+  int fuse[2];     // last-workgroup fusion of sums and small steps per side
   int pstride, slot2, extra;
   hipStream_t stream;
   PanelDev P[2];   // 0 = R (acts on R^n), 1 = L (acts on R^m)
@@ -40,15 +41,16 @@ struct hd_ctx {
   double* partials;
   double* w;       // TDOT results (pstride)
   double* zD;      // T' w (t_max)
-  double* zG;      // random-side coefficients + scratch (4 t_max)
+  double* zG;      // random-side coefficients + scratch (3 t_max)
+  double* z2;      // Ginibre: second coefficient vector of the random side
   double* head;    // rows < k of p (t_max)
   double* scal;    // [0] pivot, [1] cscale
   double* gscal;   // Ginibre: [0] nu, [1] sigma
-  double* z2;      // Ginibre: second coefficient vector of the random side
   void* B[2];      // Ginibre explicit basis vectors: B[0] (n rows) holds v_t
                    // of Q'-queries, B[1] (m rows) u_t of Q-queries
-  int64_t dim[2];  // n, m
   int* flag;
+  int* counter;    // arrival counters of the fused last-workgroup epilogues
+  double* gpart;   // group rows of the two-level fused sums
   void* ring[3];   // internal trajectory vectors for hd_run
   void* ybuf;
   void* zeros;
@@ -84,17 +86,36 @@ int hip_fail(hipError_t e) {
 
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
-// Rows per workgroup = 1024 * cpt.  HD_CPT (1, 2, 4 or 8) overrides the
-// size-based choice, for tuning.
-int pick_cpt(int64_t n) {
-  const char* e = std::getenv("HD_CPT");
-  if (e) {
-    const int v = std::atoi(e);
-    if (v == 1 || v == 2 || v == 4 || v == 8) return v;
-  }
-  if (n >= (int64_t)1 << 20) return 4;
-  if (n >= (int64_t)1 << 17) return 2;
-  return 1;
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
+// Fused sums: at most kMaxGroups groups of workgroups per launch.
+constexpr int kMaxGroups = 256;
+
+int group_size(int nwg) {
+  int g = 16;
+  while ((nwg + g - 1) / g > 32 && g < 64) g *= 2;
+  while ((nwg + g - 1) / g > kMaxGroups) g *= 2;
+  return g;
+}
+
+// Panels up to 256K rows use one row per lane (256-row workgroups, so even
+// n = 65536 fills the chip); larger ones four rows per lane in chunks of
+// 1024 rows, cpt chunks per workgroup.  HD_RPL / HD_CPT override (tuning).
+Shape pick_shape(int64_t dim, int64_t ld) {
+  Shape sh;
+  sh.rpl = dim <= ((int64_t)1 << 18) ? 1 : 4;
+  sh.cpt = sh.rpl == 1 ? 1 : (dim >= ((int64_t)1 << 20) ? 4 : 2);
+  const int rpl = env_int("HD_RPL", 0), cpt = env_int("HD_CPT", 0);
+  if (rpl == 1 || rpl == 4) sh.rpl = rpl;
+  if (sh.rpl == 1) sh.cpt = 1;
+  if (sh.rpl == 4 && (cpt == 1 || cpt == 2 || cpt == 4 || cpt == 8))
+    sh.cpt = cpt;
+  const int64_t rows = (int64_t)kWG * sh.rpl * sh.cpt;
+  sh.nwg = (int)((ld + rows - 1) / rows);
+  return sh;
 }
 
 template <typename P>
@@ -152,7 +173,7 @@ struct ProfScope {
   }
 };
 
-// ---------------------------------------------------------- Haar query --
+// ------------------------------------------------------- launch helpers --
 
 SlotRanges ranges(int s0, int n0, int s1 = 0, int n1 = 0, int s2 = 0,
                   int n2 = 0) {
@@ -166,9 +187,12 @@ SlotRanges ranges(int s0, int n0, int s1 = 0, int n1 = 0, int s2 = 0,
   return r;
 }
 
-TdotArgs tdot_base(hd_ctx* h) {
+TdotArgs tdot_base(hd_ctx* h, int side) {
   TdotArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.V = h->P[side].V;
+  a.ld = h->ld[side];
+  a.n = h->dim[side];
   a.partials = h->partials;
   a.pstride = h->pstride;
   a.slot2 = h->slot2;
@@ -183,6 +207,7 @@ PassArgs pass_base(hd_ctx* h, int side) {
   std::memset(&a, 0, sizeof(a));
   a.V = h->P[side].V;
   a.ld = h->ld[side];
+  a.n = h->dim[side];
   a.pi = h->P[side].pi;
   a.partials = h->partials;
   a.pstride = h->pstride;
@@ -191,178 +216,229 @@ PassArgs pass_base(hd_ctx* h, int side) {
   return a;
 }
 
-// Prefetch of the random side for query `step` (1-based) on panel `side`
-// holding k columns: dots of its columns with g_step over rows > k and
-// ||g_step[k+1:]||^2, into P[side].red.
-int haar_prefetch(hd_ctx* h, int side, int k, int step) {
-  TdotArgs a = tdot_base(h);
-  a.V = h->P[side].V;
-  a.ld = h->ld[side];
-  a.ncols = k;
-  a.gen = 1;
-  a.gen_step = (uint32_t)step;
-  a.lo = k;
-  a.n = h->cfg.n;
-  a.want_ss = 1;
-  {
-    ProfScope ps(h, 0, (double)h->es * (double)h->ld[side] * k);
-    LCHK(launch_tdot(h->f64, h->cpt[side], a, h->nwg[side], h->stream));
-  }
-  LCHK(launch_reduce(h->partials, h->pstride, h->nwg[side],
-                     ranges(0, k, h->extra, kNumExtra), h->P[side].red,
-                     h->stream));
-  h->pf_step[side] = step;
+SmallDataArgs small_data_args(hd_ctx* h, int side, int kp, const double* c,
+                              int k, const double* w, double* z) {
+  SmallDataArgs sd;
+  sd.T = h->P[side].T;
+  sd.tau = h->P[side].tau;
+  sd.tmax = h->cfg.t_max;
+  sd.kp = kp;
+  sd.c = c;
+  sd.k = k;
+  sd.w = w;
+  sd.z = z;
+  return sd;
+}
+
+// The sums of a pass over the partial rows into `out`, then the small step
+// `op`: inside the pass's last workgroup when the grid is small enough,
+// otherwise as separate launches after it.
+template <typename Args>
+void set_tail(hd_ctx* h, int side, Args& a, SlotRanges rg, double* out,
+              int op) {
+  std::memset(&a.tail, 0, sizeof(a.tail));
+  if (!h->fuse[side]) return;
+  a.tail.counter = h->counter;
+  a.tail.gpart = h->gpart;
+  a.tail.gsz = group_size(h->sh[side].nwg);
+  a.tail.rg = rg;
+  a.tail.out = out;
+  a.tail.op = op;
+}
+
+int after_unfused(hd_ctx* h, int side, const Tail& want) {
+  if (h->fuse[side]) return HD_OK;
+  LCHK(launch_reduce(h->partials, h->pstride, h->sh[side].nwg, want.rg,
+                     want.out, h->stream));
+  if (want.op == kTailSmallData) LCHK(launch_small_data(want.sd, h->stream));
+  if (want.op == kTailHaarSmall)
+    LCHK(launch_haar_small(h->f64, want.hs, h->stream));
+  if (want.op == kTailGinSmall)
+    LCHK(launch_gin_small(h->f64, want.gs, h->stream));
   return HD_OK;
+}
+
+int do_tdot(hd_ctx* h, int side, TdotArgs& a, Tail want, double bytes) {
+  set_tail(h, side, a, want.rg, want.out, want.op);
+  if (h->fuse[side]) {
+    a.tail.sd = want.sd;
+  }
+  {
+    ProfScope ps(h, 0, bytes);
+    LCHK(launch_tdot(h->f64, h->sh[side], a, h->stream));
+  }
+  return after_unfused(h, side, want);
+}
+
+int do_pass(hd_ctx* h, int side, int mode, PassArgs& a, Tail want,
+            int kind, double bytes) {
+  set_tail(h, side, a, want.rg, want.out, want.op);
+  if (h->fuse[side]) {
+    a.tail.hs = want.hs;
+    a.tail.gs = want.gs;
+  }
+  {
+    ProfScope ps(h, kind, bytes);
+    LCHK(launch_pass(h->f64, h->sh[side], mode, a, h->stream));
+  }
+  return after_unfused(h, side, want);
+}
+
+int do_gin_pass(hd_ctx* h, int side, GinPassArgs& a, Tail want,
+                double bytes) {
+  set_tail(h, side, a, want.rg, want.out, want.op);
+  {
+    ProfScope ps(h, 2, bytes);
+    LCHK(launch_gin_pass(h->f64, h->sh[side], a, h->stream));
+  }
+  return after_unfused(h, side, want);
+}
+
+Tail want_of(SlotRanges rg, double* out, int op) {
+  Tail t;
+  std::memset(&t, 0, sizeof(t));
+  t.rg = rg;
+  t.out = out;
+  t.op = op;
+  return t;
 }
 
 const void* panel_col(hd_ctx* h, int side, int j) {
   return (const char*)h->P[side].V + (size_t)h->es * (size_t)h->ld[side] * j;
 }
 
-// Complete the pending T column of a panel about to serve as the random
-// side: one pass of direct dots V[:, :k]' u_kp.
-int resolve_pending(hd_ctx* h, int side, int k) {
-  const int kp = h->pending[side];
-  if (kp < 0) return HD_OK;
-  if (kp > 0) {
-    TdotArgs a = tdot_base(h);
-    a.V = h->P[side].V;
-    a.ld = h->ld[side];
-    a.ncols = kp;
-    a.b = panel_col(h, side, kp);
-    a.n = side == 0 ? h->cfg.n : h->cfg.m;
-    {
-      ProfScope ps(h, 0, (double)h->es * (double)h->ld[side] * (kp + 1));
-      LCHK(launch_tdot(h->f64, h->cpt[side], a, h->nwg[side], h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[side],
-                       ranges(0, kp), h->w, h->stream));
-    SmallDataArgs sd;
-    sd.T = h->P[side].T;
-    sd.tau = h->P[side].tau;
-    sd.tmax = h->cfg.t_max;
-    sd.kp = kp;
-    sd.c = h->w;
-    sd.k = 0;
-    sd.w = nullptr;
-    sd.z = nullptr;
-    LCHK(launch_small_data(sd, h->stream));
-  }
-  (void)k;
-  h->pending[side] = -1;
+// Prefetch of the random side for query `step` on panel `side` holding k
+// columns: dots of its columns with g_step over rows > lo, and (Haar) the
+// squared norm of those rows of g_step, into P[side].red.
+int prefetch(hd_ctx* h, int side, int k, int step, int64_t lo, int want_ss) {
+  TdotArgs a = tdot_base(h, side);
+  a.ncols = k;
+  a.gen = 1;
+  a.gen_step = (uint32_t)step;
+  a.lo = lo;
+  a.want_ss = want_ss;
+  const Tail want = want_of(ranges(0, k, h->extra, want_ss ? kNumExtra : 0),
+                            h->P[side].red, kTailNone);
+  int rc = do_tdot(h, side, a, want, (double)h->es * (double)h->ld[side] * k);
+  if (rc) return rc;
+  h->pf_step[side] = step;
   return HD_OK;
 }
 
-int haar_query(hd_ctx* h, int transpose, const void* x, void* y,
-               int want_ysq) {
+// Complete the pending T column of a panel about to serve as the random
+// side: one pass of direct dots V[:, :kp]' u_kp.
+int resolve_pending(hd_ctx* h, int side) {
+  const int kp = h->pending[side];
+  h->pending[side] = -1;
+  if (kp <= 0) return HD_OK;
+  TdotArgs a = tdot_base(h, side);
+  a.ncols = kp;
+  a.b = panel_col(h, side, kp);
+  Tail want = want_of(ranges(0, kp), h->w, kTailSmallData);
+  want.sd = small_data_args(h, side, kp, h->w, 0, nullptr, nullptr);
+  return do_tdot(h, side, a, want,
+                 (double)h->es * ((double)h->ld[side] * kp + h->dim[side]));
+}
+
+// w = V_D' x (+ B_D' x for Ginibre, + V_D' u_kp for the pending column kp),
+// then T column kp and z_D = T_D' w.
+int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
+  const int kp = h->pending[ds];
+  h->pending[ds] = -1;
+  if (kD + nb2 == 0) return HD_OK;
+  TdotArgs a = tdot_base(h, ds);
+  a.ncols = kD;
+  a.V2 = nb2 ? h->B[ds] : nullptr;
+  a.ncols2 = nb2;
+  a.b = x;
+  a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
+  Tail want = want_of(ranges(0, kD + nb2, h->slot2, kp > 0 ? kp : 0), h->w,
+                      kTailSmallData);
+  want.sd = small_data_args(h, ds, kp, h->w + h->slot2, kD,
+                            kD > 0 ? h->w : nullptr, h->zD);
+  const double n = (double)h->dim[ds];
+  return do_tdot(h, ds, a, want,
+                 (double)h->es * ((double)h->ld[ds] * (kD + nb2) + n +
+                                  (kp > 0 ? n : 0.0)));
+}
+
+DynFuse no_dyn() {
+  DynFuse d;
+  std::memset(&d, 0, sizeof(d));
+  return d;
+}
+
+// ---------------------------------------------------------- Haar query --
+
+// Algorithm 2: data side D (R for y = Q x, L for y = Q' x) and random side G.
+int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
+               const DynFuse& dyn) {
   const int k = h->t;  // reflectors per side before this query
   const int step = k + 1;
   const int64_t n = h->cfg.n;
-  const int ds = transpose ? 1 : 0;  // data side
-  const int gs = 1 - ds;             // random side
+  const int ds = transpose ? 1 : 0;
+  const int gs = 1 - ds;
+  const double es = (double)h->es;
+  int rc = resolve_pending(h, gs);
+  if (rc) return rc;
   if (h->pf_step[gs] != step) {
-    int rc = haar_prefetch(h, gs, k, step);
-    if (rc) return rc;
-  }
-  {
-    int rc = resolve_pending(h, gs, k);
+    rc = prefetch(h, gs, k, step, k, 1);
     if (rc) return rc;
   }
   const bool pf = step + 1 <= h->cfg.t_max;
-  const double es = (double)h->es;
-  // 1. w = V_D' x, together with V_D' u_kp for the pending column kp; then
-  //    T column kp and z_D = T_D' w
-  if (k > 0) {
-    const int kp = h->pending[ds];
-    TdotArgs a = tdot_base(h);
-    a.V = h->P[ds].V;
-    a.ld = h->ld[ds];
-    a.ncols = k;
-    a.b = x;
-    a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
-    a.n = n;
-    {
-      ProfScope ps(h, 0, es * ((double)h->ld[ds] * k + n +
-                               (kp > 0 ? (double)n : 0.0)));
-      LCHK(launch_tdot(h->f64, h->cpt[ds], a, h->nwg[ds], h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
-                       ranges(0, k, h->slot2, kp > 0 ? kp : 0), h->w,
-                       h->stream));
-    SmallDataArgs sd;
-    sd.T = h->P[ds].T;
-    sd.tau = h->P[ds].tau;
-    sd.tmax = h->cfg.t_max;
-    sd.kp = kp;
-    sd.c = h->w + h->slot2;
-    sd.k = k;
-    sd.w = h->w;
-    sd.z = h->zD;
-    LCHK(launch_small_data(sd, h->stream));
-    h->pending[ds] = -1;
-  }
-  // 2. p = Delta_D (x - V_D z_D); new column k of V_D; prefetch for step+1
+  rc = data_tdot(h, ds, x, k, 0);
+  if (rc) return rc;
+  // p = Delta_D (x - V_D z_D); new column k of V_D; prefetch for step+1;
+  // then the scalars of R_t and L_t and the random side's coefficients
   {
     PassArgs a = pass_base(h, ds);
     a.k = k;
     a.z = h->zD;
-    a.n = n;
     a.x = x;
     a.head = h->head;
     a.pivot = h->scal;
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    {
-      ProfScope ps(h, 1, es * ((double)h->ld[ds] * k + n + (n - k)));
-      LCHK(launch_pass(h->f64, h->cpt[ds], kPassData, a, h->nwg[ds],
-                       h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
-                       ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                       h->P[ds].red, h->stream));
+    Tail want = want_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                        h->P[ds].red, kTailHaarSmall);
+    HaarSmallArgs& hs = want.hs;
+    hs.D = h->P[ds];
+    hs.G = h->P[gs];
+    hs.k = k;
+    hs.tmax = h->cfg.t_max;
+    hs.zG = h->zG;
+    hs.head = h->head;
+    hs.pivot = h->scal;
+    hs.cscale = h->scal + 1;
+    hs.key = Key{h->cfg.seed, h->cfg.trial};
+    hs.step = (uint32_t)step;
+    hs.extra = h->extra;
+    hs.flag = h->flag;
+    rc = do_pass(h, ds, kPassData, a, want, 1,
+                 es * ((double)h->ld[ds] * k + n + (n - k)));
+    if (rc) return rc;
   }
-  // 3. scalars of R_t and L_t, T/Gram columns, coefficients of the output
-  {
-    HaarSmallArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.D = h->P[ds];
-    a.G = h->P[gs];
-    a.k = k;
-    a.tmax = h->cfg.t_max;
-    a.storage_f64 = h->f64;
-    a.zG = h->zG;
-    a.head = h->head;
-    a.pivot = h->scal;
-    a.cscale = h->scal + 1;
-    a.key = Key{h->cfg.seed, h->cfg.trial};
-    a.step = (uint32_t)step;
-    a.extra = h->extra;
-    a.flag = h->flag;
-    LCHK(launch_haar_small(h->f64, a, h->stream));
-  }
-  // 4. y = (I - V_G T_G V_G') Delta_G w, w = [p[:k]; (nu/nu_G) g[k:]]
+  // y = (I - V_G T_G V_G') Delta_G w, w = [p[:k]; (nu/nu_G) g[k:]]
   {
     PassArgs a = pass_base(h, gs);
     a.k = k;
     a.z = h->zG;
-    a.n = n;
     a.head = h->head;
     a.cscale = h->scal + 1;
     a.y = y;
     a.step = (uint32_t)step;
     a.want_ysq = want_ysq;
+    a.dyn = dyn;
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    {
-      ProfScope ps(h, 2, es * ((double)h->ld[gs] * k + n + (n - k)));
-      LCHK(launch_pass(h->f64, h->cpt[gs], kPassRandHaar, a, h->nwg[gs],
-                       h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs],
-                       ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                       h->P[gs].red, h->stream));
+    const Tail want = want_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                              h->P[gs].red, kTailNone);
+    rc = do_pass(h, gs, kPassRandHaar, a, want, 2,
+                 es * ((double)h->ld[gs] * k + n + (n - k) +
+                       (dyn.kind ? 2.0 * n : 0.0)));
+    if (rc) return rc;
   }
   h->t = step;
   h->r = step;
@@ -373,14 +449,17 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y,
   return HD_OK;
 }
 
-// Algorithm 1 query.  Data side D (R for y = Q x, L for y = Q' x) gets a new
+// -------------------------------------------------------- Ginibre query --
+
+// Algorithm 1.  The data side D (R for y = Q x, L for y = Q' x) gets a new
 // reflector from p = D_k..D_1 x; the random side G answers
 //   y = sigma sum_i (v_i' x) u_i
-// with the implicit basis vectors of G (reflector products applied to
-// coefficients h = B_D' x from the TDOT pass) and the explicit ones in B[G]
+// with the implicit basis vectors of G (reflector products applied to the
+// coefficients h = B_D' x of the TDOT pass) and the explicit ones in B[G]
 // (coefficients = the head of p, because the data-type basis vectors are
 // R_1..R_j e_j), and stores the new explicit vector (L..L Z g or R..R Z g).
-int gin_query(hd_ctx* h, int transpose, const void* x, void* y) {
+int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
+              const DynFuse& dyn) {
   const int ds = transpose ? 1 : 0;
   const int gs = 1 - ds;
   const int kD = ds == 0 ? h->r : h->l;
@@ -388,102 +467,47 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y) {
   const int step = h->t + 1;
   const int64_t nD = h->dim[ds], nG = h->dim[gs];
   const double es = (double)h->es;
-  {
-    int rc = resolve_pending(h, gs, kG);
+  int rc = resolve_pending(h, gs);
+  if (rc) return rc;
+  if (kG > 0 && h->pf_step[gs] != step) {
+    rc = prefetch(h, gs, kG, step, kG - 1, 0);
     if (rc) return rc;
   }
-  if (kG > 0 && h->pf_step[gs] != step) {
-    TdotArgs a = tdot_base(h);
-    a.V = h->P[gs].V;
-    a.ld = h->ld[gs];
-    a.ncols = kG;
-    a.gen = 1;
-    a.gen_step = (uint32_t)step;
-    a.lo = kG - 1;
-    a.n = nG;
-    {
-      ProfScope ps(h, 0, es * (double)h->ld[gs] * kG);
-      LCHK(launch_tdot(h->f64, h->cpt[gs], a, h->nwg[gs], h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs], ranges(0, kG),
-                       h->P[gs].red, h->stream));
-  }
   const bool pf = step + 1 <= h->cfg.t_max;
-  // 1. w = V_D' x (+ pending column dots), h = B_D' x
-  if (kD + kG > 0) {
-    const int kp = h->pending[ds];
-    TdotArgs a = tdot_base(h);
-    a.V = h->P[ds].V;
-    a.ld = h->ld[ds];
-    a.ncols = kD;
-    a.V2 = h->B[ds];
-    a.ncols2 = kG;
-    a.b = x;
-    a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
-    a.n = nD;
-    {
-      ProfScope ps(h, 0, es * ((double)h->ld[ds] * (kD + kG) + nD +
-                               (kp > 0 ? (double)nD : 0.0)));
-      LCHK(launch_tdot(h->f64, h->cpt[ds], a, h->nwg[ds], h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
-                       ranges(0, kD + kG, h->slot2, kp > 0 ? kp : 0), h->w,
-                       h->stream));
+  rc = data_tdot(h, ds, x, kD, kG);
+  if (rc) return rc;
+  if (kD == 0 && kG > 0 && !h->fuse[ds]) {
+    // z_D is empty; nothing to do beyond the sums data_tdot launched
   }
-  {
-    SmallDataArgs sd;
-    sd.T = h->P[ds].T;
-    sd.tau = h->P[ds].tau;
-    sd.tmax = h->cfg.t_max;
-    sd.kp = h->pending[ds];
-    sd.c = h->w + h->slot2;
-    sd.k = kD;
-    sd.w = kD > 0 ? h->w : nullptr;
-    sd.z = h->zD;
-    LCHK(launch_small_data(sd, h->stream));
-    h->pending[ds] = -1;
-  }
-  // 2. p = Delta_D (x - V_D z_D), new column kD of V_D, prefetch for G-use
   {
     PassArgs a = pass_base(h, ds);
     a.k = kD;
     a.z = h->zD;
-    a.n = nD;
     a.x = x;
     a.head = h->head;
     a.pivot = h->scal;
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kD;
-    {
-      ProfScope ps(h, 1, es * ((double)h->ld[ds] * kD + nD + (nD - kD)));
-      LCHK(launch_pass(h->f64, h->cpt[ds], kPassData, a, h->nwg[ds],
-                       h->stream));
-    }
-    LCHK(launch_reduce(h->partials, h->pstride, h->nwg[ds],
-                       ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
-                       h->P[ds].red, h->stream));
+    Tail want = want_of(ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
+                        h->P[ds].red, kTailGinSmall);
+    GinSmallArgs& gsa = want.gs;
+    gsa.D = h->P[ds];
+    gsa.G = h->P[gs];
+    gsa.k = kD;
+    gsa.l = kG;
+    gsa.tmax = h->cfg.t_max;
+    gsa.h = h->w + kD;
+    gsa.z1 = h->zG;
+    gsa.z2 = h->z2;
+    gsa.pivot = h->scal;
+    gsa.scal = h->gscal;
+    gsa.D_extra = h->extra;
+    gsa.flag = h->flag;
+    rc = do_pass(h, ds, kPassData, a, want, 1,
+                 es * ((double)h->ld[ds] * kD + nD + (nD - kD)));
+    if (rc) return rc;
   }
-  // 3. scalars of the new reflector; coefficients of the random side
-  {
-    GinSmallArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.D = h->P[ds];
-    a.G = h->P[gs];
-    a.k = kD;
-    a.l = kG;
-    a.tmax = h->cfg.t_max;
-    a.h = h->w + kD;
-    a.z1 = h->zG;
-    a.z2 = h->z2;
-    a.head = h->head;
-    a.pivot = h->scal;
-    a.scal = h->gscal;
-    a.D_extra = h->extra;
-    a.flag = h->flag;
-    LCHK(launch_gin_small(h->f64, a, h->stream));
-  }
-  // 4. y and the new explicit basis vector
   {
     GinPassArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -502,19 +526,19 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y) {
     a.y = y;
     a.key = Key{h->cfg.seed, h->cfg.trial};
     a.step = (uint32_t)step;
+    a.dyn = dyn;
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kG - 1;
     a.partials = h->partials;
     a.pstride = h->pstride;
     a.extra = h->extra;
-    {
-      ProfScope ps(h, 2, es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG));
-      LCHK(launch_gin_pass(h->f64, h->cpt[gs], a, h->nwg[gs], h->stream));
-    }
-    if (pf && kG > 0)
-      LCHK(launch_reduce(h->partials, h->pstride, h->nwg[gs], ranges(0, kG),
-                         h->P[gs].red, h->stream));
+    const Tail want = want_of(ranges(0, pf ? kG : 0), h->P[gs].red,
+                              kTailNone);
+    rc = do_gin_pass(h, gs, a, want,
+                     es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
+                           (dyn.kind ? 2.0 * nG : 0.0)));
+    if (rc) return rc;
   }
   h->t = step;
   if (ds == 0)
@@ -538,15 +562,14 @@ int check_query(hd_ctx* h, int transpose, const void* x, const void* y) {
   return HD_OK;
 }
 
-int query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq) {
+int query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
+          const DynFuse& dyn) {
   if (h->cfg.ensemble == HD_HAAR)
-    return haar_query(h, transpose, x, y, want_ysq);
-  return gin_query(h, transpose, x, y);
+    return haar_query(h, transpose, x, y, want_ysq, dyn);
+  return gin_query(h, transpose, x, y, dyn);
 }
 
 }  // namespace
-
-// ------------------------------------------------------------------ ABI --
 
 extern "C" {
 
@@ -591,12 +614,12 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   h->extra = h->slot2 + tm + 1;
   h->pstride = h->extra + kNumExtra;
   int maxwg = 1;
+  const int fuse_env = env_int("HD_FUSE", 1);
   for (int s = 0; s < 2; ++s) {
     h->ld[s] = round_up(dims[s], kChunk);
-    h->cpt[s] = pick_cpt(dims[s]);
-    const int64_t rb = (int64_t)kChunk * h->cpt[s];
-    h->nwg[s] = (int)((h->ld[s] + rb - 1) / rb);
-    if (h->nwg[s] > maxwg) maxwg = h->nwg[s];
+    h->sh[s] = pick_shape(dims[s], h->ld[s]);
+    h->fuse[s] = fuse_env != 0;
+    if (h->sh[s].nwg > maxwg) maxwg = h->sh[s].nwg;
   }
   int rc = HD_OK;
 #define ALLOC(ptr, bytes)                                   \
@@ -635,6 +658,8 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
       ALLOC(h->B[s], (size_t)h->es * (size_t)h->ld[s] * (size_t)tm);
   }
   ALLOC(h->flag, sizeof(int) * 4);
+  ALLOC(h->counter, sizeof(int) * (1 + kMaxGroups));
+  ALLOC(h->gpart, sizeof(double) * (size_t)kMaxGroups * h->pstride);
 #undef ALLOC
   for (int s = 0; s < 3; ++s) {
     double* p = s < 2 ? h->P[s].pi : h->gscal + 1;
@@ -686,13 +711,13 @@ int hd_set_stream(hd_handle h, void* stream) {
 int hd_step(hd_handle h, const void* x, void* y) {
   int rc = check_query(h, 0, x, y);
   if (rc) return rc;
-  return query(h, 0, x, y, 0);
+  return query(h, 0, x, y, 0, no_dyn());
 }
 
 int hd_apply_T(hd_handle h, const void* x, void* y) {
   int rc = check_query(h, 1, x, y);
   if (rc) return rc;
-  return query(h, 1, x, y, 0);
+  return query(h, 1, x, y, 0, no_dyn());
 }
 
 int hd_status(hd_handle h) {
@@ -780,8 +805,21 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
   for (int t = 1; t <= T; ++t) {
     const int transpose = (dyn->pattern == HD_PATTERN_ALT && t % 2 == 0);
     void* y = traj_y ? (char*)traj_y + (size_t)(t - 1) * vb : h->ybuf;
-    int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE);
+    const void* xprev = t == 1 ? xprev0 : xrow(t - 1);
+    DynFuse fz = no_dyn();
+    if (dyn->kind == HD_DYN_TANH || dyn->kind == HD_DYN_SOFT_HIST) {
+      // element-wise maps run in the random-side pass epilogue
+      fz.kind = dyn->kind;
+      fz.a = dyn->a;
+      fz.b = dyn->b;
+      fz.x = xrow(t);
+      fz.xprev = xprev;
+      fz.xnext = xrow(t + 1);
+    }
+    int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE,
+                   fz);
     if (rc) return rc;
+    if (fz.kind) continue;
     DynArgs d;
     d.kind = dyn->kind;
     d.a = dyn->a;

@@ -137,6 +137,59 @@ __device__ __forceinline__ double block_column_sums(double (&v)[CG],
   return out;
 }
 
+// ------------------------------------------------ cross-workgroup sums ---
+
+// Called by every thread of a workgroup after it has written its share of
+// some result: returns true in exactly one of the `expected` workgroups that
+// arrive at this counter, the last, after making the others' writes visible
+// to it; the counter is reset for the next launch.  Release/acquire is by
+// agent-scope fences around a relaxed atomic, so it also holds across XCDs.
+__device__ __forceinline__ bool arrive_last(int* counter, int expected) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int ticket = atomicAdd(counter, 1);
+    is_last = (ticket == expected - 1) ? 1 : 0;
+    if (is_last) *counter = 0;
+  }
+  __syncthreads();
+  const bool last = is_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// out[slot] = sum_{w0 <= w < w1} P[w * pstride + slot] in increasing w, one
+// thread per slot; loads are issued eight rows at a time.
+__device__ __forceinline__ void reduce_rows(const double* P, int pstride,
+                                            int w0, int w1, SlotRanges rg,
+                                            double* out) {
+  const int total = rg.count[0] + rg.count[1] + rg.count[2];
+  for (int s = threadIdx.x; s < total; s += kWG) {
+    int slot;
+    if (s < rg.count[0])
+      slot = rg.start[0] + s;
+    else if (s - rg.count[0] < rg.count[1])
+      slot = rg.start[1] + (s - rg.count[0]);
+    else
+      slot = rg.start[2] + (s - rg.count[0] - rg.count[1]);
+    const double* col = P + slot;
+    double acc = 0.0;
+    int w = w0;
+    for (; w + 8 <= w1; w += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = col[(int64_t)(w + q) * pstride];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    for (; w < w1; ++w) acc += col[(int64_t)w * pstride];
+    out[slot] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- loads ---
 
 __device__ __forceinline__ void load4(const float* __restrict__ p,
@@ -156,6 +209,19 @@ __device__ __forceinline__ void load4(const double* __restrict__ p,
   out[1] = a.y;
   out[2] = b.x;
   out[3] = b.y;
+}
+
+// RPL consecutive panel entries of one lane (RPL = 4: one 16-byte load for
+// FP32, two for FP64; RPL = 1: one element).
+template <int RPL, typename T>
+__device__ __forceinline__ void load_rows(const T* __restrict__ p,
+                                          double (&out)[RPL]) {
+  if constexpr (RPL == 4) {
+    load4(p, out);
+  } else {
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) out[e] = (double)p[e];
+  }
 }
 
 }  // namespace hd

@@ -6,9 +6,9 @@
 
 namespace hd {
 
-constexpr int kWG = 256;         // threads per workgroup (4 waves of 64)
+constexpr int kWG = 256;  // threads per workgroup (4 waves of 64)
 constexpr int kWaves = kWG / 64;
-constexpr int kChunk = kWG * 4;  // rows per workgroup per chunk (4 per lane)
+constexpr int kChunk = kWG * 4;  // panel row padding quantum (1024 rows)
 
 // Layout of the per-workgroup partial-sum rows and of the reduced vectors.
 // A row has `pstride` doubles: slots [0, slot2) hold the column dots with the
@@ -21,67 +21,17 @@ enum ExtraSlot {
   kNumExtra = 4
 };
 
+// Up to three ranges [start, start + count) of slots.
+struct SlotRanges {
+  int start[3];
+  int count[3];
+};
+
 struct Key {
   uint32_t k0, k1;
 };
 
-// Partial dots of panel columns with a right-hand side b (from memory, or the
-// Philox draw of `gen_step` when gen != 0), over rows r with lo < r < n
-// (lo = -1 for all rows).  Two column segments share the rows.  When b2 is
-// set, the columns of the first segment are also dotted with b2 (a stored
-// panel column), into slots slot2 + j.
-struct TdotArgs {
-  const void* V;
-  int64_t ld;
-  int ncols;
-  const void* V2;
-  int ncols2;
-  const void* b;
-  const void* b2;
-  int slot2;
-  int gen;
-  Key key;
-  uint32_t gen_step;
-  int64_t lo;
-  int64_t n;
-  int want_ss;  // also sum of fl(b_i)^2 -> slot extra + kSlotPFSS
-  double* partials;
-  int pstride;
-  int extra;
-};
-
-// One GEMV-N pass over a panel (columns 0..k-1) producing an output vector,
-// writing the new column k, and the fused prefetch dots of columns 0..k with
-// the next draw over rows > pf_cut.
-enum PassMode { kPassData = 0, kPassRandHaar = 1 };
-
-struct PassArgs {
-  void* V;
-  int64_t ld;
-  int k;
-  const double* z;   // k coefficients
-  const double* pi;  // prefix sign products pi[0..k]
-  int64_t n;
-  // data mode: out = Delta (x - V z)
-  const void* x;
-  double* head;   // rows < k of the output (FP64)
-  double* pivot;  // row k of the output (FP64)
-  // random (Haar) mode: y = Delta w - V z, w = [head; cscale * g_step]
-  const double* cscale;
-  void* y;
-  Key key;
-  uint32_t step;
-  int want_ysq;
-  // fused prefetch
-  int pf;
-  uint32_t pf_step;
-  int64_t pf_cut;
-  double* partials;
-  int pstride;
-  int extra;
-};
-
-// Per-panel device state of the compact-WY representation.
+// Per-side device state of the compact-WY representation.
 struct PanelDev {
   void* V;        // ld x t_max, column-major
   int64_t ld;
@@ -108,6 +58,128 @@ struct SmallDataArgs {
   double* z;        // out (k)
 };
 
+struct HaarSmallArgs {
+  PanelDev D, G;
+  int k;
+  int tmax;
+  double* zG;       // out: coefficients for the random-side pass (k);
+                    // zG + tmax and zG + 2 tmax are scratch
+  const double* head;
+  const double* pivot;
+  double* cscale;   // out: nu / nu_G
+  Key key;
+  uint32_t step;
+  int extra;
+  int* flag;
+};
+
+// Scalars of the data-side reflector and the coefficients of the random side
+// of a Ginibre query.
+struct GinSmallArgs {
+  PanelDev D, G;
+  int k;            // data-side reflectors before this query
+  int l;            // random-side reflectors
+  int tmax;
+  const double* h;  // l coefficients of the implicit random-side basis
+  double* z1;       // out (l); z1 + tmax, z1 + 2 tmax are scratch
+  double* z2;       // out (l)
+  const double* pivot;
+  double* scal;     // out: [0] nu; [1] sigma (set by the host)
+  int D_extra;      // offset of the extra slots in D.red
+  int* flag;
+};
+
+// What the last workgroup of a pass does after it has summed the partial
+// rows (when `counter` is set; otherwise the host launches k_reduce and the
+// small kernel separately).
+enum TailOp { kTailNone = 0, kTailSmallData = 1, kTailHaarSmall = 2,
+              kTailGinSmall = 3 };
+
+// The partial rows are summed by a two-level tree: the last workgroup of
+// each group of `gsz` consecutive workgroups sums its group's rows into
+// gpart, and the last of those sums the group rows into `out`.
+struct Tail {
+  int* counter;    // [0]: top level, [1 + g]: group g
+  double* gpart;   // one row of pstride doubles per group
+  int gsz;
+  SlotRanges rg;
+  double* out;
+  int op;
+  SmallDataArgs sd;
+  HaarSmallArgs hs;
+  GinSmallArgs gs;
+};
+
+// Element-wise map f_t fused into the random-side epilogue (kind 0: none).
+enum DynKind { kDynNone = 0, kDynTanh = 1, kDynSoftHist = 2, kDynNormalize = 3 };
+
+struct DynFuse {
+  int kind;
+  double a, b;
+  const void* x;      // x_t
+  const void* xprev;  // x_{t-1}
+  void* xnext;        // x_{t+1}
+};
+
+// Partial dots of panel columns with a right-hand side b (from memory, or the
+// Philox draw of `gen_step` when gen != 0), over rows r with lo < r < n
+// (lo = -1 for all rows).  Two column segments share the rows.  When b2 is
+// set, the columns of the first segment are also dotted with b2 (a stored
+// panel column), into slots slot2 + j.
+struct TdotArgs {
+  const void* V;
+  int64_t ld;
+  int ncols;
+  const void* V2;
+  int ncols2;
+  const void* b;
+  const void* b2;
+  int slot2;
+  int gen;
+  Key key;
+  uint32_t gen_step;
+  int64_t lo;
+  int64_t n;
+  int want_ss;  // also sum of fl(b_i)^2 -> slot extra + kSlotPFSS
+  double* partials;
+  int pstride;
+  int extra;
+  Tail tail;
+};
+
+// One GEMV-N pass over a panel (columns 0..k-1) producing an output vector,
+// writing the new column k, and the fused prefetch dots of columns 0..k with
+// the next draw over rows > pf_cut.
+enum PassMode { kPassData = 0, kPassRandHaar = 1 };
+
+struct PassArgs {
+  void* V;
+  int64_t ld;
+  int k;
+  const double* z;   // k coefficients
+  const double* pi;  // prefix sign products pi[0..k]
+  int64_t n;
+  // data mode: out = Delta (x - V z)
+  const void* x;
+  double* head;   // rows < k of the output (FP64)
+  double* pivot;  // row k of the output (FP64)
+  // random (Haar) mode: y = Delta w - V z, w = [head; cscale * g_step]
+  const double* cscale;
+  void* y;
+  Key key;
+  uint32_t step;
+  int want_ysq;
+  DynFuse dyn;
+  // fused prefetch
+  int pf;
+  uint32_t pf_step;
+  int64_t pf_cut;
+  double* partials;
+  int pstride;
+  int extra;
+  Tail tail;
+};
+
 // Random-side pass of a Ginibre query (Algorithm 1).  With G the random side
 // (l = k reflectors in V, Delta = diag(pi[min(i+1,l)])) and g the draw:
 //   u   = Delta [0_l; g[l:]] - V z1                (new explicit basis vector)
@@ -131,48 +203,15 @@ struct GinPassArgs {
   void* y;
   Key key;
   uint32_t step;
+  DynFuse dyn;
   int pf;
   uint32_t pf_step;
   int64_t pf_cut;
   double* partials;
   int pstride;
   int extra;
+  Tail tail;
 };
-
-// Scalars of the data-side reflector and the coefficients of the random side
-// of a Ginibre query (one workgroup).
-struct GinSmallArgs {
-  PanelDev D, G;
-  int k;            // data-side reflectors before this query
-  int l;            // random-side reflectors
-  int tmax;
-  const double* h;  // l coefficients of the implicit random-side basis
-  double* z1;       // out (l)
-  double* z2;       // out (l); z1 + tmax .. are scratch
-  const double* head;
-  const double* pivot;
-  double* scal;     // out: [0] nu, [1] sigma (set by the host)
-  int D_extra;      // offset of the extra slots in D.red
-  int* flag;
-};
-
-struct HaarSmallArgs {
-  PanelDev D, G;
-  int k;
-  int tmax;
-  int storage_f64;
-  double* zG;       // out: coefficients for the random-side pass (k);
-                    // zG + tmax and zG + 2 tmax are scratch
-  const double* head;
-  const double* pivot;
-  double* cscale;   // out: nu / nu_G
-  Key key;
-  uint32_t step;
-  int extra;
-  int* flag;
-};
-
-enum DynKind { kDynNone = 0, kDynTanh = 1, kDynSoftHist = 2, kDynNormalize = 3 };
 
 struct DynArgs {
   int kind;
@@ -185,22 +224,22 @@ struct DynArgs {
   const double* ysq;  // normalise: ||y||^2
 };
 
-int launch_tdot(int f64, int cpt, const TdotArgs& a, int nwg,
-                hipStream_t s);
-int launch_pass(int f64, int cpt, int mode, const PassArgs& a, int nwg,
-                hipStream_t s);
-// Fixed-order sums over workgroups of the slots in up to three ranges
-// [start, start + count) of the partial rows, into out[slot].
-struct SlotRanges {
-  int start[3];
-  int count[3];
+// Launch shape of a panel pass: rows per lane (1 or 4), chunks of 256 * rpl
+// rows per workgroup, and the number of workgroups.
+struct Shape {
+  int rpl;
+  int cpt;
+  int nwg;
 };
+
+int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s);
+int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
+                hipStream_t s);
+int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s);
 int launch_reduce(const double* partials, int pstride, int nwg,
                   const SlotRanges& r, double* out, hipStream_t s);
 int launch_small_data(const SmallDataArgs& a, hipStream_t s);
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);
-int launch_gin_pass(int f64, int cpt, const GinPassArgs& a, int nwg,
-                    hipStream_t s);
 int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s);
 int launch_dyn(int f64, const DynArgs& a, hipStream_t s);
 int launch_fill(double* p, double v, int64_t count, hipStream_t s);

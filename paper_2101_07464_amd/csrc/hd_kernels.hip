@@ -9,15 +9,19 @@
 // (the -sign(v1) factor of eq. (Householder) commutes with every later
 // reflector, so all of them collect into Delta).
 //
-// Hot kernels stream the panel once per pass with 16-byte loads, four rows
-// per lane, and keep every accumulation in FP64:
-//   k_tdot  : w = V' b (per-workgroup partials; column sums by a wave
-//             reduce-scatter, then LDS across the four waves)
-//   k_pass  : out = Delta a - V z (GEMV-N), writes the new panel column and
-//             the fused dot products with the next query's Philox draw.
-// Cross-workgroup sums go through k_reduce in a fixed order, so results are
-// bitwise reproducible run to run.  Small FP64 kernels (one workgroup)
-// update the triangular factor T and the Gram matrix of each panel.
+// Panel kernels stream the panel once per pass, RPL rows per lane (4: one
+// 16-byte load per column for FP32; 1 for small panels, to give them more
+// workgroups), and keep every accumulation in FP64:
+//   k_tdot     : w = V' b (per-workgroup partials; column sums by a wave
+//                reduce-scatter, then LDS across the four waves)
+//   k_pass     : out = Delta a - V z (GEMV-N); writes the new panel column
+//                and the dot products with the next query's Philox draw
+//   k_gin_pass : the random side of a Ginibre query (two GEMV-N plus the
+//                explicit basis panel)
+// Cross-workgroup sums are fixed-order, so results are bitwise reproducible
+// run to run.  For small grids the last workgroup to finish does that sum and
+// the query's FP64 scalar step itself (Tail); otherwise k_reduce and a small
+// one-workgroup kernel follow.
 #include <hip/hip_runtime.h>
 
 #include "hd_device.hpp"
@@ -27,237 +31,30 @@ namespace hd {
 
 constexpr int kCG = 16;  // columns per group in the panel loops
 
-// ------------------------------------------------------------------ TDOT --
-
-template <typename T, int CPT, bool GEN, bool TWO>
-__global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
-  __shared__ double lds[kWaves * kCG];
-  __shared__ double scr[kWaves];
-  const int tid = threadIdx.x;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kChunk * CPT);
-  double b[CPT][4];
-  double b2[CPT][4];
-  bool cvalid[CPT];
-  double ss = 0.0;
-  const PhiloxKey key{a.key.k0, a.key.k1};
+// Draws g_step[i] for the RPL rows i0..i0+RPL-1 of one lane; rows outside
+// (lo, n) get 0.  Values are rounded to the storage type when `round`.
+template <typename T, int RPL>
+__device__ __forceinline__ void draw_rows(PhiloxKey key, uint32_t step,
+                                          int64_t i0, int64_t lo, int64_t n,
+                                          bool round, double (&out)[RPL]) {
 #pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kChunk;
-    cvalid[c] = row0 < a.ld;
-    const int64_t i0 = row0 + 4 * tid;
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    if (GEN) {
-      if (cvalid[c] && i0 < a.n && i0 + 3 > a.lo)
-        normals4(key, a.gen_step, 0u, (uint64_t)(i0 >> 2), g);
-    }
+  for (int e = 0; e < RPL; ++e) out[e] = 0.0;
+  if (i0 >= n || i0 + RPL - 1 <= lo) return;
+  double g[4];
+  normals4(key, step, 0u, (uint64_t)(i0 >> 2), g);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + e;
-      double v = 0.0, v2 = 0.0;
-      if (cvalid[c] && i > a.lo && i < a.n) {
-        v = GEN ? (double)(T)g[e] : (double)((const T*)a.b)[i];
-      }
-      if (TWO && cvalid[c] && i < a.n) v2 = (double)((const T*)a.b2)[i];
-      b[c][e] = v;
-      b2[c][e] = v2;
-      ss += v * v;
-    }
-  }
-  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
-#pragma unroll 1
-  for (int seg = 0; seg < 2; ++seg) {
-    const T* V = (const T*)(seg ? a.V2 : a.V);
-    const int nc = seg ? a.ncols2 : a.ncols;
-    const int slot0 = seg ? a.ncols : 0;
-#pragma unroll 1
-    for (int j0 = 0; j0 < nc; j0 += kCG) {
-      double acc[kCG], acc2[kCG];
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        acc[jj] = 0.0;
-        acc2[jj] = 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        if (!cvalid[c]) continue;
-        const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
-#pragma unroll
-        for (int jj = 0; jj < kCG; ++jj) {
-          const int j = min(j0 + jj, nc - 1);
-          double v[4];
-          load4(V + (int64_t)j * a.ld + r, v);
-          acc[jj] += v[0] * b[c][0] + v[1] * b[c][1] + v[2] * b[c][2] +
-                     v[3] * b[c][3];
-          if (TWO && seg == 0)
-            acc2[jj] += v[0] * b2[c][0] + v[1] * b2[c][1] + v[2] * b2[c][2] +
-                        v[3] * b2[c][3];
-        }
-      }
-      const double s = block_column_sums<kCG>(acc, lds);
-      if (tid < kCG && j0 + tid < nc) out[slot0 + j0 + tid] = s;
-      if (TWO && seg == 0) {
-        const double s2 = block_column_sums<kCG>(acc2, lds);
-        if (tid < kCG && j0 + tid < nc) out[a.slot2 + j0 + tid] = s2;
-      }
-    }
-  }
-  if (a.want_ss) {
-    const double s = block_sum(ss, scr);
-    if (tid == 0) out[a.extra + kSlotPFSS] = s;
+  for (int e = 0; e < RPL; ++e) {
+    const int64_t i = i0 + e;
+    const double v = g[(RPL == 4) ? e : (int)(i & 3)];
+    if (i > lo && i < n) out[e] = round ? (double)(T)v : v;
   }
 }
 
-// ---------------------------------------------------------------- GEMV-N --
-
-template <typename T, int CPT, int MODE>
-__global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
-  __shared__ double lds[kWaves * kCG];
-  __shared__ double scr[kWaves];
-  const int tid = threadIdx.x;
-  const int k = a.k;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kChunk * CPT);
-  T* __restrict__ V = (T*)a.V;
-  const PhiloxKey key{a.key.k0, a.key.k1};
-  double acc[CPT][4];
-  double gn[CPT][4];
-  bool cvalid[CPT];
-  double pfss = 0.0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kChunk;
-    cvalid[c] = row0 < a.ld;
-    const int64_t i0 = row0 + 4 * tid;
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    if (a.pf && cvalid[c] && i0 < a.n && i0 + 3 > a.pf_cut)
-      normals4(key, a.pf_step, 0u, (uint64_t)(i0 >> 2), g);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + e;
-      acc[c][e] = 0.0;
-      double v = 0.0;
-      if (a.pf && cvalid[c] && i > a.pf_cut && i < a.n) v = (double)(T)g[e];
-      gn[c][e] = v;
-      pfss += v * v;
-    }
-  }
-  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
-
-#pragma unroll 1
-  for (int j0 = 0; j0 < k; j0 += kCG) {
-    double zz[kCG];
-    double pacc[kCG];
-#pragma unroll
-    for (int jj = 0; jj < kCG; ++jj) {
-      zz[jj] = (j0 + jj < k) ? a.z[j0 + jj] : 0.0;
-      pacc[jj] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        const int j = min(j0 + jj, k - 1);
-        double v[4];
-        load4(V + (int64_t)j * a.ld + r, v);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          acc[c][e] -= v[e] * zz[jj];
-          pacc[jj] += v[e] * gn[c][e];
-        }
-      }
-    }
-    if (a.pf) {
-      const double s = block_column_sums<kCG>(pacc, lds);
-      if (tid < kCG && j0 + tid < k) out[j0 + tid] = s;
-    }
-  }
-
-  // Epilogue: form the output rows, write the new column k, and the extras.
-  double ssq = 0.0, pfnew = 0.0, ysq = 0.0;
-  const double pik = a.pi[k];
-  const double cs = (MODE == kPassRandHaar) ? *a.cscale : 0.0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    if (!cvalid[c]) continue;
-    const int64_t i0 = blk0 + (int64_t)c * kChunk + 4 * tid;
-    double gt[4] = {0.0, 0.0, 0.0, 0.0};
-    if (MODE == kPassRandHaar && i0 < a.n && i0 + 3 >= k)
-      normals4(key, a.step, 0u, (uint64_t)(i0 >> 2), gt);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + e;
-      if (i >= a.n) continue;
-      const double sg = (i < k) ? a.pi[i + 1] : pik;
-      if (MODE == kPassData) {
-        const double p = sg * ((double)((const T*)a.x)[i] + acc[c][e]);
-        if (i < k) {
-          a.head[i] = p;
-        } else if (i == k) {
-          *a.pivot = p;
-        } else {
-          const T ps = (T)p;
-          V[(int64_t)k * a.ld + i] = ps;
-          const double pd = (double)ps;
-          ssq += pd * pd;
-          pfnew += pd * gn[c][e];
-        }
-      } else {
-        const double w = (i < k) ? a.head[i] : cs * gt[e];
-        const T ys = (T)(sg * w + acc[c][e]);
-        ((T*)a.y)[i] = ys;
-        ysq += (double)ys * (double)ys;
-        if (i > k) {
-          const T gs = (T)gt[e];
-          V[(int64_t)k * a.ld + i] = gs;
-          pfnew += (double)gs * gn[c][e];
-        }
-      }
-    }
-  }
-  if (MODE == kPassData) {
-    const double s = block_sum(ssq, scr);
-    if (tid == 0) out[a.extra + kSlotSS] = s;
-  } else if (a.want_ysq) {
-    const double s = block_sum(ysq, scr);
-    if (tid == 0) out[a.extra + kSlotYSQ] = s;
-  }
-  if (a.pf) {
-    const double s1 = block_sum(pfnew, scr);
-    const double s2 = block_sum(pfss, scr);
-    if (tid == 0) {
-      out[k] = s1;
-      out[a.extra + kSlotPFSS] = s2;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- reduce --
-
-__global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ P,
-                                                int pstride, int nwg,
-                                                SlotRanges rg,
-                                                double* __restrict__ out) {
-  __shared__ double scr[kWaves];
-  int b = blockIdx.x, slot = -1;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    if (slot < 0) {
-      if (b < rg.count[q])
-        slot = rg.start[q] + b;
-      else
-        b -= rg.count[q];
-    }
-  }
-  double s = 0.0;
-  for (int w = threadIdx.x; w < nwg; w += kWG) s += P[(int64_t)w * pstride + slot];
-  s = block_sum(s, scr);
-  if (threadIdx.x == 0) out[slot] = s;
-}
+// ------------------------------------------------- small FP64 steps ------
 
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
 // Schreiber and Van Loan), then z = T' w for the leading k x k block.
-__global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
+__device__ void small_data_body(const SmallDataArgs& a) {
   const int tm = a.tmax, kp = a.kp;
   if (kp > 0) {
     const double tau = a.tau[kp];
@@ -267,6 +64,7 @@ __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
       a.T[j + (int64_t)kp * tm] = -tau * s;
     }
   }
+  __threadfence_block();
   __syncthreads();
   if (a.w) {
     for (int j = threadIdx.x; j < a.k; j += kWG) {
@@ -277,45 +75,49 @@ __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
   }
 }
 
-// --------------------------------------------------- Haar scalar updates --
-//
-// After the data-side pass of query t (k = t-1 reflectors stored per panel):
-//  data side  : nu = ||p[k:]||, s = sign(p_k), stored pivot u_k = p_k + s nu,
-//               tau = 2/||u||^2 (from the stored entries).  Its T column is
-//               completed later from direct dots V'u_k (k_small_data).
-//  random side: L_t = H_t(g_t) from the prefetched dots V'g over rows > k and
-//               ||g[k+1:]||^2; its T column; s_vec = V' Delta w for
-//               w = [p[:k]; (nu/||g[k:]||) g[k:]], the vector L_t R_t p_t of
-//               eq. (Qtxt) before L_1..L_{t-1}; and z_G = T_G s_vec.
+// Data-side reflector of a query from p (pivot p_k, ss = ||p[k+1:]||^2 of the
+// stored entries): nu = ||p[k:]||, s = sign(p_k), stored pivot u_k = p_k + s nu
+// rounded to storage, tau = 2/||u||^2 from the stored entries.  nu = 0 gives
+// the identity (tau = 0, no sign).  Written by one thread; returns nu.
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
-  __shared__ double sh[8];
+__device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
+                                 double pk, int* flag) {
+  T* V = (T*)D.V;
+  const double nu = sqrt(ss + pk * pk);
+  double s = 1.0, tau = 0.0, up = 0.0;
+  if (nu > 0.0) {
+    s = pk >= 0.0 ? 1.0 : -1.0;
+    up = (double)(T)(pk + s * nu);
+    tau = 2.0 / (ss + up * up);
+  }
+  if (!isfinite(nu) || !isfinite(tau)) flag[0] = 1;
+  V[(int64_t)k * D.ld + k] = (T)up;
+  D.tau[k] = tau;
+  D.nu[k] = nu;
+  D.piv[k] = pk;
+  D.sgn[k] = s;
+  D.pi[k + 1] = nu > 0.0 ? D.pi[k] * (-s) : D.pi[k];
+  D.T[k + (int64_t)k * tm] = tau;
+  return nu;
+}
+
+// Haar, after the data-side pass of query t (k = t-1 reflectors per panel):
+// the data reflector R_t, then L_t = H_t(g_t) from the prefetched dots V'g
+// over rows > k and ||g[k+1:]||^2, its T column, s_vec = V' Delta w for
+// w = [p[:k]; (nu/||g[k:]||) g[k:]] (the vector L_t R_t p_t of eq. (Qtxt)
+// before L_1..L_{t-1}), and z_G = T_G s_vec.
+template <typename T>
+__device__ void haar_small_body(const HaarSmallArgs& a) {
+  __shared__ double sh[4];
   const int k = a.k, tid = threadIdx.x, tm = a.tmax;
-  T* VD = (T*)a.D.V;
   T* VG = (T*)a.G.V;
-  const int64_t ldD = a.D.ld, ldG = a.G.ld;
+  const int64_t ldG = a.G.ld;
   double* cG = a.zG + tm;
   double* sv = a.zG + 2 * tm;
   if (tid == 0) {
-    const double ss = a.D.red[a.extra + kSlotSS];
-    const double pk = *a.pivot;
-    const double nu = sqrt(ss + pk * pk);
-    double s = 1.0, tau = 0.0, up = 0.0;
-    if (nu > 0.0) {
-      s = pk >= 0.0 ? 1.0 : -1.0;
-      up = (double)(T)(pk + s * nu);
-      tau = 2.0 / (ss + up * up);
-    }
-    if (!isfinite(nu) || !isfinite(tau)) a.flag[0] = 1;
-    VD[(int64_t)k * ldD + k] = (T)up;
-    a.D.tau[k] = tau;
-    a.D.nu[k] = nu;
-    a.D.piv[k] = pk;
-    a.D.sgn[k] = s;
-    // an identity reflector (nu = 0) contributes no sign
-    a.D.pi[k + 1] = nu > 0.0 ? a.D.pi[k] * (-s) : a.D.pi[k];
-    a.D.T[k + (int64_t)k * tm] = tau;
-
+    const double nu = data_reflector<T>(a.D, k, tm,
+                                        a.D.red[a.extra + kSlotSS], *a.pivot,
+                                        a.flag);
     const PhiloxKey key{a.key.k0, a.key.k1};
     const double gk = normal_at(key, a.step, 0u, (uint64_t)k);
     const double ssG = a.G.red[a.extra + kSlotPFSS];
@@ -340,6 +142,7 @@ __global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
     sh[2] = gk;
     sh[3] = upG;
   }
+  __threadfence_block();
   __syncthreads();
   const double tauG = sh[0], cs = sh[1], gk = sh[2], upG = sh[3];
   const double piGk = a.G.pi[k];
@@ -352,6 +155,7 @@ __global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
     cG[j] = gdot + (double)colG[k] * upG;
     sv[j] = hg + piGk * cs * (gdot + (double)colG[k] * gk);
   }
+  __threadfence_block();
   __syncthreads();
   for (int j = tid; j < k; j += kWG) {
     double tG = 0.0, zz = 0.0;
@@ -365,35 +169,315 @@ __global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
   }
 }
 
+// Ginibre: the data reflector, then the random-side coefficients
+// s1 = V_G' Delta_G [0; g] = pi_l (prefetched dots over rows >= l),
+// s2 = V_G' Delta_G h (head rows only) + nu s1; z1 = T_G s1, z2 = T_G s2.
+template <typename T>
+__device__ void gin_small_body(const GinSmallArgs& a) {
+  __shared__ double sh[1];
+  const int k = a.k, l = a.l, tid = threadIdx.x, tm = a.tmax;
+  const T* VG = (const T*)a.G.V;
+  const int64_t ldG = a.G.ld;
+  double* s1 = a.z1 + tm;
+  double* s2 = a.z1 + 2 * tm;
+  if (tid == 0) {
+    const double nu = data_reflector<T>(a.D, k, tm,
+                                        a.D.red[a.D_extra + kSlotSS], *a.pivot,
+                                        a.flag);
+    a.scal[0] = nu;
+    sh[0] = nu;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const double nu = sh[0];
+  const double pil = a.G.pi[l];
+  for (int j = tid; j < l; j += kWG) {
+    const T* col = VG + (int64_t)j * ldG;
+    double hs = 0.0;
+    for (int i = 0; i < l; ++i) hs += (double)col[i] * a.G.pi[i + 1] * a.h[i];
+    const double v1 = pil * a.G.red[j];
+    s1[j] = v1;
+    s2[j] = hs + nu * v1;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int j = tid; j < l; j += kWG) {
+    double z1 = 0.0, z2 = 0.0;
+    for (int q = j; q < l; ++q) {
+      const double tjq = a.G.T[j + (int64_t)q * tm];
+      z1 += tjq * s1[q];
+      z2 += tjq * s2[q];
+    }
+    a.z1[j] = z1;
+    a.z2[j] = z2;
+  }
+}
+
+// Last-workgroup epilogue of a panel kernel: sum the partial rows in a fixed
+// order, then run the query's small step.  A no-op without a counter.
+template <typename T>
+__device__ __forceinline__ void run_tail(const Tail& tl,
+                                         const double* partials, int pstride) {
+  if (!tl.counter) return;
+  const int nwg = gridDim.x;
+  const int g = blockIdx.x / tl.gsz;
+  const int ng = (nwg + tl.gsz - 1) / tl.gsz;
+  const int w0 = g * tl.gsz, w1 = min(w0 + tl.gsz, nwg);
+  if (!arrive_last(tl.counter + 1 + g, w1 - w0)) return;
+  if (ng == 1) {
+    reduce_rows(partials, pstride, w0, w1, tl.rg, tl.out);
+  } else {
+    reduce_rows(partials, pstride, w0, w1, tl.rg,
+                tl.gpart + (int64_t)g * pstride);
+    if (!arrive_last(tl.counter, ng)) return;
+    reduce_rows(tl.gpart, pstride, 0, ng, tl.rg, tl.out);
+  }
+  __threadfence();
+  if (tl.op == kTailSmallData)
+    small_data_body(tl.sd);
+  else if (tl.op == kTailHaarSmall)
+    haar_small_body<T>(tl.hs);
+  else if (tl.op == kTailGinSmall)
+    gin_small_body<T>(tl.gs);
+}
+
+// Element-wise map f_t on one row (y already rounded to storage).
+__device__ __forceinline__ double dyn_row(const DynFuse& d, double yi,
+                                          double xi, double xpi) {
+  if (d.kind == kDynTanh) return tanh(d.a * yi) + d.b * xi;
+  const double m = fabs(yi) - d.a;
+  return (m > 0.0 ? copysign(m, yi) : 0.0) + d.b * xpi;
+}
+
+// ------------------------------------------------------------------ TDOT --
+
+template <typename T, int RPL, int CPT, bool GEN, bool TWO>
+__global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
+  constexpr int kRows = kWG * RPL;
+  __shared__ double lds[kWaves * kCG];
+  __shared__ double scr[kWaves];
+  const int tid = threadIdx.x;
+  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
+  double b[CPT][RPL];
+  double b2[CPT][RPL];
+  bool cvalid[CPT];
+  double ss = 0.0;
+  const PhiloxKey key{a.key.k0, a.key.k1};
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t row0 = blk0 + (int64_t)c * kRows;
+    cvalid[c] = row0 < a.ld;
+    const int64_t i0 = row0 + RPL * tid;
+    if (GEN) {
+      draw_rows<T, RPL>(key, a.gen_step, i0, a.lo, cvalid[c] ? a.n : 0, true,
+                        b[c]);
+    }
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const int64_t i = i0 + e;
+      const bool in = cvalid[c] && i < a.n;
+      if (!GEN) b[c][e] = (in && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
+      b2[c][e] = (TWO && in) ? (double)((const T*)a.b2)[i] : 0.0;
+      ss += b[c][e] * b[c][e];
+    }
+  }
+  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
+#pragma unroll 1
+  for (int seg = 0; seg < 2; ++seg) {
+    const T* V = (const T*)(seg ? a.V2 : a.V);
+    const int nc = seg ? a.ncols2 : a.ncols;
+    const int slot0 = seg ? a.ncols : 0;
+#pragma unroll 1
+    for (int j0 = 0; j0 < nc; j0 += kCG) {
+      double acc[kCG], acc2[kCG];
+#pragma unroll
+      for (int jj = 0; jj < kCG; ++jj) {
+        acc[jj] = 0.0;
+        acc2[jj] = 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        if (!cvalid[c]) continue;
+        const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
+#pragma unroll
+        for (int jj = 0; jj < kCG; ++jj) {
+          const int j = min(j0 + jj, nc - 1);
+          double v[RPL];
+          load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            acc[jj] += v[e] * b[c][e];
+            if (TWO) acc2[jj] += v[e] * b2[c][e];
+          }
+        }
+      }
+      const double s = block_column_sums<kCG>(acc, lds);
+      if (tid < kCG && j0 + tid < nc) out[slot0 + j0 + tid] = s;
+      if (TWO && seg == 0) {
+        const double s2 = block_column_sums<kCG>(acc2, lds);
+        if (tid < kCG && j0 + tid < nc) out[a.slot2 + j0 + tid] = s2;
+      }
+    }
+  }
+  if (a.want_ss) {
+    const double s = block_sum(ss, scr);
+    if (tid == 0) out[a.extra + kSlotPFSS] = s;
+  }
+  run_tail<T>(a.tail, a.partials, a.pstride);
+}
+
+// ---------------------------------------------------------------- GEMV-N --
+
+template <typename T, int RPL, int CPT, int MODE>
+__global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
+  constexpr int kRows = kWG * RPL;
+  __shared__ double lds[kWaves * kCG];
+  __shared__ double scr[kWaves];
+  const int tid = threadIdx.x;
+  const int k = a.k;
+  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
+  T* __restrict__ V = (T*)a.V;
+  const PhiloxKey key{a.key.k0, a.key.k1};
+  double acc[CPT][RPL];
+  double gn[CPT][RPL];
+  bool cvalid[CPT];
+  double pfss = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t row0 = blk0 + (int64_t)c * kRows;
+    cvalid[c] = row0 < a.ld;
+    draw_rows<T, RPL>(key, a.pf_step, row0 + RPL * tid, a.pf_cut,
+                      (a.pf && cvalid[c]) ? a.n : 0, true, gn[c]);
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      acc[c][e] = 0.0;
+      pfss += gn[c][e] * gn[c][e];
+    }
+  }
+  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
+
+#pragma unroll 1
+  for (int j0 = 0; j0 < k; j0 += kCG) {
+    double zz[kCG];
+    double pacc[kCG];
+#pragma unroll
+    for (int jj = 0; jj < kCG; ++jj) {
+      zz[jj] = (j0 + jj < k) ? a.z[j0 + jj] : 0.0;
+      pacc[jj] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      if (!cvalid[c]) continue;
+      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
+#pragma unroll
+      for (int jj = 0; jj < kCG; ++jj) {
+        const int j = min(j0 + jj, k - 1);
+        double v[RPL];
+        load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          acc[c][e] -= v[e] * zz[jj];
+          pacc[jj] += v[e] * gn[c][e];
+        }
+      }
+    }
+    if (a.pf) {
+      const double s = block_column_sums<kCG>(pacc, lds);
+      if (tid < kCG && j0 + tid < k) out[j0 + tid] = s;
+    }
+  }
+
+  // Epilogue: form the output rows, write the new column k, and the extras.
+  double ssq = 0.0, pfnew = 0.0, ysq = 0.0;
+  const double pik = a.pi[k];
+  const double cs = (MODE == kPassRandHaar) ? *a.cscale : 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    if (!cvalid[c]) continue;
+    const int64_t i0 = blk0 + (int64_t)c * kRows + RPL * tid;
+    double gt[RPL];
+    if (MODE == kPassRandHaar)
+      draw_rows<T, RPL>(key, a.step, i0, (int64_t)k - 1, a.n, false, gt);
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) {
+      const int64_t i = i0 + e;
+      if (i >= a.n) continue;
+      const double sg = (i < k) ? a.pi[i + 1] : pik;
+      if (MODE == kPassData) {
+        const double p = sg * ((double)((const T*)a.x)[i] + acc[c][e]);
+        if (i < k) {
+          a.head[i] = p;
+        } else if (i == k) {
+          *a.pivot = p;
+        } else {
+          const T ps = (T)p;
+          V[(int64_t)k * a.ld + i] = ps;
+          const double pd = (double)ps;
+          ssq += pd * pd;
+          pfnew += pd * gn[c][e];
+        }
+      } else {
+        const double w = (i < k) ? a.head[i] : cs * gt[e];
+        const T ys = (T)(sg * w + acc[c][e]);
+        ((T*)a.y)[i] = ys;
+        ysq += (double)ys * (double)ys;
+        if (a.dyn.kind) {
+          const double xi = (double)((const T*)a.dyn.x)[i];
+          const double xpi = a.dyn.kind == kDynSoftHist
+                                 ? (double)((const T*)a.dyn.xprev)[i]
+                                 : 0.0;
+          ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
+        }
+        if (i > k) {
+          const T gs = (T)gt[e];
+          V[(int64_t)k * a.ld + i] = gs;
+          pfnew += (double)gs * gn[c][e];
+        }
+      }
+    }
+  }
+  if (MODE == kPassData) {
+    const double s = block_sum(ssq, scr);
+    if (tid == 0) out[a.extra + kSlotSS] = s;
+  } else if (a.want_ysq) {
+    const double s = block_sum(ysq, scr);
+    if (tid == 0) out[a.extra + kSlotYSQ] = s;
+  }
+  if (a.pf) {
+    const double s1 = block_sum(pfnew, scr);
+    const double s2 = block_sum(pfss, scr);
+    if (tid == 0) {
+      out[k] = s1;
+      out[a.extra + kSlotPFSS] = s2;
+    }
+  }
+  run_tail<T>(a.tail, a.partials, a.pstride);
+}
+
 // ------------------------------------------------- Ginibre random side --
 
-template <typename T, int CPT>
+template <typename T, int RPL, int CPT>
 __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
+  constexpr int kRows = kWG * RPL;
   __shared__ double lds[kWaves * kCG];
   const int tid = threadIdx.x;
   const int k = a.k, nb = a.nb;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kChunk * CPT);
+  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
   const T* __restrict__ V = (const T*)a.V;
   T* __restrict__ B = (T*)a.B;
   const PhiloxKey key{a.key.k0, a.key.k1};
-  double acc1[CPT][4], acc2[CPT][4], gn[CPT][4];
+  double acc1[CPT][RPL], acc2[CPT][RPL], gn[CPT][RPL];
   bool cvalid[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kChunk;
+    const int64_t row0 = blk0 + (int64_t)c * kRows;
     cvalid[c] = row0 < a.ld;
-    const int64_t i0 = row0 + 4 * tid;
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    if (a.pf && cvalid[c] && i0 < a.n && i0 + 3 > a.pf_cut)
-      normals4(key, a.pf_step, 0u, (uint64_t)(i0 >> 2), g);
+    draw_rows<T, RPL>(key, a.pf_step, row0 + RPL * tid, a.pf_cut,
+                      (a.pf && cvalid[c]) ? a.n : 0, true, gn[c]);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + e;
+    for (int e = 0; e < RPL; ++e) {
       acc1[c][e] = 0.0;
       acc2[c][e] = 0.0;
-      gn[c][e] = (a.pf && cvalid[c] && i > a.pf_cut && i < a.n)
-                     ? (double)(T)g[e]
-                     : 0.0;
     }
   }
   double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
@@ -412,14 +496,14 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
+      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
 #pragma unroll
       for (int jj = 0; jj < kCG; ++jj) {
         const int j = min(j0 + jj, k - 1);
-        double v[4];
-        load4(V + (int64_t)j * a.ld + r, v);
+        double v[RPL];
+        load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < RPL; ++e) {
           acc1[c][e] -= v[e] * za[jj];
           acc2[c][e] -= v[e] * zb[jj];
           pacc[jj] += v[e] * gn[c][e];
@@ -441,14 +525,14 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kChunk + 4 * tid;
+      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
 #pragma unroll
       for (int jj = 0; jj < kCG; ++jj) {
         const int j = min(j0 + jj, nb - 1);
-        double v[4];
-        load4(B + (int64_t)j * a.ld + r, v);
+        double v[RPL];
+        load_rows<RPL>(B + (int64_t)j * a.ld + r, v);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc2[c][e] += v[e] * cv[jj];
+        for (int e = 0; e < RPL; ++e) acc2[c][e] += v[e] * cv[jj];
       }
     }
   }
@@ -457,81 +541,68 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     if (!cvalid[c]) continue;
-    const int64_t i0 = blk0 + (int64_t)c * kChunk + 4 * tid;
-    double gt[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i0 < a.n && i0 + 3 >= k)
-      normals4(key, a.step, 0u, (uint64_t)(i0 >> 2), gt);
+    const int64_t i0 = blk0 + (int64_t)c * kRows + RPL * tid;
+    double gt[RPL];
+    draw_rows<T, RPL>(key, a.step, i0, (int64_t)k - 1, a.n, false, gt);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < RPL; ++e) {
       const int64_t i = i0 + e;
       if (i >= a.n) continue;
       const double sg = (i < k) ? a.pi[i + 1] : pik;
-      const double gi = (i >= k) ? gt[e] : 0.0;
+      const double gi = gt[e];
       B[(int64_t)nb * a.ld + i] = (T)(sg * gi + acc1[c][e]);
       const double hv = (i < k) ? a.h[i] : 0.0;
-      ((T*)a.y)[i] = (T)(sigma * (acc2[c][e] + sg * (hv + nu * gi)));
+      const T ys = (T)(sigma * (acc2[c][e] + sg * (hv + nu * gi)));
+      ((T*)a.y)[i] = ys;
+      if (a.dyn.kind) {
+        const double xi = (double)((const T*)a.dyn.x)[i];
+        const double xpi = a.dyn.kind == kDynSoftHist
+                               ? (double)((const T*)a.dyn.xprev)[i]
+                               : 0.0;
+        ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
+      }
     }
   }
+  run_tail<T>(a.tail, a.partials, a.pstride);
 }
 
-// Data-side scalars (as for Haar) and the random-side coefficients of a
-// Ginibre query: s1 = V_G' Delta_G [0; g] = pi_l * (prefetched dots),
-// s2 = V_G' Delta_G h (head rows only) + nu s1; z1 = T_G s1, z2 = T_G s2.
+// ------------------------------------------------- standalone kernels ----
+
+__global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ P,
+                                                int pstride, int nwg,
+                                                SlotRanges rg,
+                                                double* __restrict__ out) {
+  __shared__ double scr[kWaves];
+  int b = blockIdx.x, slot = -1;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (slot < 0) {
+      if (b < rg.count[q])
+        slot = rg.start[q] + b;
+      else
+        b -= rg.count[q];
+    }
+  }
+  double s = 0.0;
+  for (int w = threadIdx.x; w < nwg; w += kWG)
+    s += P[(int64_t)w * pstride + slot];
+  s = block_sum(s, scr);
+  if (threadIdx.x == 0) out[slot] = s;
+}
+
+__global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
+  small_data_body(a);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
+  haar_small_body<T>(a);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_gin_small(GinSmallArgs a) {
-  __shared__ double sh[2];
-  const int k = a.k, l = a.l, tid = threadIdx.x, tm = a.tmax;
-  T* VD = (T*)a.D.V;
-  const T* VG = (const T*)a.G.V;
-  const int64_t ldD = a.D.ld, ldG = a.G.ld;
-  double* s1 = a.z1 + tm;
-  double* s2 = a.z1 + 2 * tm;
-  if (tid == 0) {
-    const double ss = a.D.red[a.D_extra + kSlotSS];
-    const double pk = *a.pivot;
-    const double nu = sqrt(ss + pk * pk);
-    double s = 1.0, tau = 0.0, up = 0.0;
-    if (nu > 0.0) {
-      s = pk >= 0.0 ? 1.0 : -1.0;
-      up = (double)(T)(pk + s * nu);
-      tau = 2.0 / (ss + up * up);
-    }
-    if (!isfinite(nu) || !isfinite(tau)) a.flag[0] = 1;
-    VD[(int64_t)k * ldD + k] = (T)up;
-    a.D.tau[k] = tau;
-    a.D.nu[k] = nu;
-    a.D.piv[k] = pk;
-    a.D.sgn[k] = s;
-    a.D.pi[k + 1] = nu > 0.0 ? a.D.pi[k] * (-s) : a.D.pi[k];
-    a.D.T[k + (int64_t)k * tm] = tau;
-    a.scal[0] = nu;
-    sh[0] = nu;
-  }
-  __syncthreads();
-  const double nu = sh[0];
-  const double pil = a.G.pi[l];
-  for (int j = tid; j < l; j += kWG) {
-    const T* col = VG + (int64_t)j * ldG;
-    double hs = 0.0;
-    for (int i = 0; i < l; ++i) hs += (double)col[i] * a.G.pi[i + 1] * a.h[i];
-    const double v1 = pil * a.G.red[j];
-    s1[j] = v1;
-    s2[j] = hs + nu * v1;
-  }
-  __syncthreads();
-  for (int j = tid; j < l; j += kWG) {
-    double z1 = 0.0, z2 = 0.0;
-    for (int q = j; q < l; ++q) {
-      const double tjq = a.G.T[j + (int64_t)q * tm];
-      z1 += tjq * s1[q];
-      z2 += tjq * s2[q];
-    }
-    a.z1[j] = z1;
-    a.z2[j] = z2;
-  }
+  gin_small_body<T>(a);
 }
-
-// ------------------------------------------------------------- dynamics --
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_dyn(DynArgs a) {
@@ -570,108 +641,129 @@ __global__ __launch_bounds__(kWG) void k_fill(double* p, double v,
 
 // ------------------------------------------------------------- launchers --
 
-#define HD_CHECK_LAUNCH()                                    \
-  do {                                                       \
-    hipError_t e_ = hipGetLastError();                       \
-    if (e_ != hipSuccess) return (int)e_;                    \
+#define HD_CHECK_LAUNCH()                 \
+  do {                                    \
+    hipError_t e_ = hipGetLastError();    \
+    if (e_ != hipSuccess) return (int)e_; \
   } while (0)
 
+// Launch shapes (rpl, cpt): (1,1) for small panels, (4, 1|2|4|8) otherwise.
 template <typename T, bool GEN, bool TWO>
-static int tdot_cpt(int cpt, const TdotArgs& a, int nwg, hipStream_t s) {
-  switch (cpt) {
-    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 1, GEN, TWO>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 2, GEN, TWO>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, GEN, TWO>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 8, GEN, TWO>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    default: return -1;
-  }
+static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s) {
+  const dim3 g(sh.nwg), b(kWG);
+  if (sh.rpl == 1 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 1, 1, GEN, TWO>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 1, GEN, TWO>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 2, GEN, TWO>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 4)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 4, GEN, TWO>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 8)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 8, GEN, TWO>), g, b, 0, s, a);
+  else
+    return -1;
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 template <typename T>
-static int tdot_t(int cpt, const TdotArgs& a, int nwg, hipStream_t s) {
-  if (a.gen) return tdot_cpt<T, true, false>(cpt, a, nwg, s);
-  if (a.b2) return tdot_cpt<T, false, true>(cpt, a, nwg, s);
-  return tdot_cpt<T, false, false>(cpt, a, nwg, s);
+static int tdot_t(Shape sh, const TdotArgs& a, hipStream_t s) {
+  if (a.gen) return tdot_shape<T, true, false>(sh, a, s);
+  if (a.b2) return tdot_shape<T, false, true>(sh, a, s);
+  return tdot_shape<T, false, false>(sh, a, s);
 }
 
-int launch_tdot(int f64, int cpt, const TdotArgs& a, int nwg, hipStream_t s) {
-  return f64 ? tdot_t<double>(cpt, a, nwg, s) : tdot_t<float>(cpt, a, nwg, s);
+int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s) {
+  return f64 ? tdot_t<double>(sh, a, s) : tdot_t<float>(sh, a, s);
 }
 
 template <typename T, int MODE>
-static int pass_cpt(int cpt, const PassArgs& a, int nwg, hipStream_t s) {
-  switch (cpt) {
-    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 1, MODE>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 2, MODE>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, MODE>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 8, MODE>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    default: return -1;
-  }
+static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s) {
+  const dim3 g(sh.nwg), b(kWG);
+  if (sh.rpl == 1 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 1, 1, MODE>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 1, MODE>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 2, MODE>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 4)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 4, MODE>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 8)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 8, MODE>), g, b, 0, s, a);
+  else
+    return -1;
   HD_CHECK_LAUNCH();
   return 0;
 }
 
-int launch_pass(int f64, int cpt, int mode, const PassArgs& a, int nwg,
+int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                 hipStream_t s) {
   if (f64)
-    return mode == kPassData ? pass_cpt<double, kPassData>(cpt, a, nwg, s)
-                             : pass_cpt<double, kPassRandHaar>(cpt, a, nwg, s);
-  return mode == kPassData ? pass_cpt<float, kPassData>(cpt, a, nwg, s)
-                           : pass_cpt<float, kPassRandHaar>(cpt, a, nwg, s);
+    return mode == kPassData ? pass_shape<double, kPassData>(sh, a, s)
+                             : pass_shape<double, kPassRandHaar>(sh, a, s);
+  return mode == kPassData ? pass_shape<float, kPassData>(sh, a, s)
+                           : pass_shape<float, kPassRandHaar>(sh, a, s);
+}
+
+template <typename T>
+static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
+  const dim3 g(sh.nwg), b(kWG);
+  if (sh.rpl == 1 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 1, 1>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 1)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 1>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 2)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 2>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 4)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 4>), g, b, 0, s, a);
+  else if (sh.rpl == 4 && sh.cpt == 8)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 8>), g, b, 0, s, a);
+  else
+    return -1;
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s) {
+  return f64 ? gin_shape<double>(sh, a, s) : gin_shape<float>(sh, a, s);
 }
 
 int launch_reduce(const double* partials, int pstride, int nwg,
                   const SlotRanges& r, double* out, hipStream_t s) {
   const int total = r.count[0] + r.count[1] + r.count[2];
   if (total <= 0) return 0;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce), dim3(total), dim3(kWG), 0, s, partials, pstride, nwg, r, out);
+  hipLaunchKernelGGL(k_reduce, dim3(total), dim3(kWG), 0, s, partials,
+                     pstride, nwg, r, out);
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 int launch_small_data(const SmallDataArgs& a, hipStream_t s) {
   if (a.kp <= 0 && (!a.w || a.k <= 0)) return 0;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_data), dim3(1), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_small_data, dim3(1), dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s) {
   if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<double>), dim3(1), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<double>), dim3(1),
+                       dim3(kWG), 0, s, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<float>), dim3(1), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_haar_small<float>), dim3(1),
+                       dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
-}
-
-template <typename T>
-static int gin_pass_cpt(int cpt, const GinPassArgs& a, int nwg,
-                        hipStream_t s) {
-  switch (cpt) {
-    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 1>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 2>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 8>), dim3(nwg), dim3(kWG), 0, s, a); break;
-    default: return -1;
-  }
-  HD_CHECK_LAUNCH();
-  return 0;
-}
-
-int launch_gin_pass(int f64, int cpt, const GinPassArgs& a, int nwg,
-                    hipStream_t s) {
-  return f64 ? gin_pass_cpt<double>(cpt, a, nwg, s)
-             : gin_pass_cpt<float>(cpt, a, nwg, s);
 }
 
 int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s) {
   if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<double>), dim3(1), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<double>), dim3(1),
+                       dim3(kWG), 0, s, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<float>), dim3(1), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_small<float>), dim3(1),
+                       dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -681,9 +773,11 @@ int launch_dyn(int f64, const DynArgs& a, hipStream_t s) {
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dyn<double>), dim3((int)blocks), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dyn<double>), dim3((int)blocks),
+                       dim3(kWG), 0, s, a);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dyn<float>), dim3((int)blocks), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dyn<float>), dim3((int)blocks),
+                       dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -692,7 +786,7 @@ int launch_fill(double* p, double v, int64_t count, hipStream_t s) {
   if (count <= 0) return 0;
   int64_t blocks = (count + kWG - 1) / kWG;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fill), dim3((int)blocks), dim3(kWG), 0, s, p, v, count);
+  hipLaunchKernelGGL(k_fill, dim3((int)blocks), dim3(kWG), 0, s, p, v, count);
   HD_CHECK_LAUNCH();
   return 0;
 }
