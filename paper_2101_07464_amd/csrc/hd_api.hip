@@ -32,7 +32,6 @@ struct hd_ctx {
   int64_t dim[2];  // n (side 0, R), m (side 1, L)
   int64_t ld[2];   // leading dimension of the panels of each side
   Shape sh[2];     // launch shape of the panel kernels of each side
-  int fuse[2];     // last-workgroup fusion of sums and small steps per side
   int pstride, slot2, extra;
   hipStream_t stream;
   PanelDev P[2];   // 0 = R (acts on R^n), 1 = L (acts on R^m)
@@ -49,8 +48,6 @@ struct hd_ctx {
   void* B[2];      // Ginibre explicit basis vectors: B[0] (n rows) holds v_t
                    // of Q'-queries, B[1] (m rows) u_t of Q-queries
   int* flag;
-  int* counter;    // arrival counters of the fused last-workgroup epilogues
-  double* gpart;   // group rows of the two-level fused sums
   void* ring[3];   // internal trajectory vectors for hd_run
   void* ybuf;
   void* zeros;
@@ -91,15 +88,6 @@ int env_int(const char* name, int dflt) {
   return e ? std::atoi(e) : dflt;
 }
 
-// Fused sums: at most kMaxGroups groups of workgroups per launch.
-constexpr int kMaxGroups = 256;
-
-int group_size(int nwg) {
-  int g = 16;
-  while ((nwg + g - 1) / g > 32 && g < 64) g *= 2;
-  while ((nwg + g - 1) / g > kMaxGroups) g *= 2;
-  return g;
-}
 
 // Panels up to 256K rows use one row per lane (256-row workgroups, so even
 // n = 65536 fills the chip); larger ones four rows per lane in chunks of
@@ -230,77 +218,60 @@ SmallDataArgs small_data_args(hd_ctx* h, int side, int kp, const double* c,
   return sd;
 }
 
-// The sums of a pass over the partial rows into `out`, then the small step
-// `op`: inside the pass's last workgroup when the grid is small enough,
-// otherwise as separate launches after it.
-template <typename Args>
-void set_tail(hd_ctx* h, int side, Args& a, SlotRanges rg, double* out,
-              int op) {
-  std::memset(&a.tail, 0, sizeof(a.tail));
-  if (!h->fuse[side]) return;
-  a.tail.counter = h->counter;
-  a.tail.gpart = h->gpart;
-  a.tail.gsz = group_size(h->sh[side].nwg);
-  a.tail.rg = rg;
-  a.tail.out = out;
-  a.tail.op = op;
-}
+// What follows a panel pass: the fixed-order sums of its partial rows into
+// `out` (k_reduce), then optionally one small FP64 step.
+struct After {
+  SlotRanges rg;
+  double* out;
+  int op;  // 0 none, 1 small_data, 2 haar_small, 3 gin_small
+  SmallDataArgs sd;
+  HaarSmallArgs hs;
+  GinSmallArgs gs;
+};
 
-int after_unfused(hd_ctx* h, int side, const Tail& want) {
-  if (h->fuse[side]) return HD_OK;
-  LCHK(launch_reduce(h->partials, h->pstride, h->sh[side].nwg, want.rg,
-                     want.out, h->stream));
-  if (want.op == kTailSmallData) LCHK(launch_small_data(want.sd, h->stream));
-  if (want.op == kTailHaarSmall)
-    LCHK(launch_haar_small(h->f64, want.hs, h->stream));
-  if (want.op == kTailGinSmall)
-    LCHK(launch_gin_small(h->f64, want.gs, h->stream));
-  return HD_OK;
-}
-
-int do_tdot(hd_ctx* h, int side, TdotArgs& a, Tail want, double bytes) {
-  set_tail(h, side, a, want.rg, want.out, want.op);
-  if (h->fuse[side]) {
-    a.tail.sd = want.sd;
-  }
-  {
-    ProfScope ps(h, 0, bytes);
-    LCHK(launch_tdot(h->f64, h->sh[side], a, h->stream));
-  }
-  return after_unfused(h, side, want);
-}
-
-int do_pass(hd_ctx* h, int side, int mode, PassArgs& a, Tail want,
-            int kind, double bytes) {
-  set_tail(h, side, a, want.rg, want.out, want.op);
-  if (h->fuse[side]) {
-    a.tail.hs = want.hs;
-    a.tail.gs = want.gs;
-  }
-  {
-    ProfScope ps(h, kind, bytes);
-    LCHK(launch_pass(h->f64, h->sh[side], mode, a, h->stream));
-  }
-  return after_unfused(h, side, want);
-}
-
-int do_gin_pass(hd_ctx* h, int side, GinPassArgs& a, Tail want,
-                double bytes) {
-  set_tail(h, side, a, want.rg, want.out, want.op);
-  {
-    ProfScope ps(h, 2, bytes);
-    LCHK(launch_gin_pass(h->f64, h->sh[side], a, h->stream));
-  }
-  return after_unfused(h, side, want);
-}
-
-Tail want_of(SlotRanges rg, double* out, int op) {
-  Tail t;
+After after_of(SlotRanges rg, double* out, int op) {
+  After t;
   std::memset(&t, 0, sizeof(t));
   t.rg = rg;
   t.out = out;
   t.op = op;
   return t;
+}
+
+int run_after(hd_ctx* h, int side, const After& af) {
+  LCHK(launch_reduce(h->partials, h->pstride, h->sh[side].nwg, af.rg, af.out,
+                     h->stream));
+  if (af.op == 1) LCHK(launch_small_data(af.sd, h->stream));
+  if (af.op == 2) LCHK(launch_haar_small(h->f64, af.hs, h->stream));
+  if (af.op == 3) LCHK(launch_gin_small(h->f64, af.gs, h->stream));
+  return HD_OK;
+}
+
+int do_tdot(hd_ctx* h, int side, const TdotArgs& a, const After& af,
+            double bytes) {
+  {
+    ProfScope ps(h, 0, bytes);
+    LCHK(launch_tdot(h->f64, h->sh[side], a, h->stream));
+  }
+  return run_after(h, side, af);
+}
+
+int do_pass(hd_ctx* h, int side, int mode, const PassArgs& a,
+            const After& af, int kind, double bytes) {
+  {
+    ProfScope ps(h, kind, bytes);
+    LCHK(launch_pass(h->f64, h->sh[side], mode, a, h->stream));
+  }
+  return run_after(h, side, af);
+}
+
+int do_gin_pass(hd_ctx* h, int side, const GinPassArgs& a, const After& af,
+                double bytes) {
+  {
+    ProfScope ps(h, 2, bytes);
+    LCHK(launch_gin_pass(h->f64, h->sh[side], a, h->stream));
+  }
+  return run_after(h, side, af);
 }
 
 const void* panel_col(hd_ctx* h, int side, int j) {
@@ -317,8 +288,8 @@ int prefetch(hd_ctx* h, int side, int k, int step, int64_t lo, int want_ss) {
   a.gen_step = (uint32_t)step;
   a.lo = lo;
   a.want_ss = want_ss;
-  const Tail want = want_of(ranges(0, k, h->extra, want_ss ? kNumExtra : 0),
-                            h->P[side].red, kTailNone);
+  const After want = after_of(ranges(0, k, h->extra, want_ss ? kNumExtra : 0),
+                            h->P[side].red, 0);
   int rc = do_tdot(h, side, a, want, (double)h->es * (double)h->ld[side] * k);
   if (rc) return rc;
   h->pf_step[side] = step;
@@ -334,7 +305,7 @@ int resolve_pending(hd_ctx* h, int side) {
   TdotArgs a = tdot_base(h, side);
   a.ncols = kp;
   a.b = panel_col(h, side, kp);
-  Tail want = want_of(ranges(0, kp), h->w, kTailSmallData);
+  After want = after_of(ranges(0, kp), h->w, 1);
   want.sd = small_data_args(h, side, kp, h->w, 0, nullptr, nullptr);
   return do_tdot(h, side, a, want,
                  (double)h->es * ((double)h->ld[side] * kp + h->dim[side]));
@@ -352,8 +323,8 @@ int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
   a.ncols2 = nb2;
   a.b = x;
   a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
-  Tail want = want_of(ranges(0, kD + nb2, h->slot2, kp > 0 ? kp : 0), h->w,
-                      kTailSmallData);
+  After want = after_of(ranges(0, kD + nb2, h->slot2, kp > 0 ? kp : 0), h->w,
+                      1);
   want.sd = small_data_args(h, ds, kp, h->w + h->slot2, kD,
                             kD > 0 ? h->w : nullptr, h->zD);
   const double n = (double)h->dim[ds];
@@ -400,8 +371,8 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    Tail want = want_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                        h->P[ds].red, kTailHaarSmall);
+    After want = after_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                        h->P[ds].red, 2);
     HaarSmallArgs& hs = want.hs;
     hs.D = h->P[ds];
     hs.G = h->P[gs];
@@ -433,8 +404,8 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    const Tail want = want_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                              h->P[gs].red, kTailNone);
+    const After want = after_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
+                              h->P[gs].red, 0);
     rc = do_pass(h, gs, kPassRandHaar, a, want, 2,
                  es * ((double)h->ld[gs] * k + n + (n - k) +
                        (dyn.kind ? 2.0 * n : 0.0)));
@@ -476,9 +447,6 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
   const bool pf = step + 1 <= h->cfg.t_max;
   rc = data_tdot(h, ds, x, kD, kG);
   if (rc) return rc;
-  if (kD == 0 && kG > 0 && !h->fuse[ds]) {
-    // z_D is empty; nothing to do beyond the sums data_tdot launched
-  }
   {
     PassArgs a = pass_base(h, ds);
     a.k = kD;
@@ -489,8 +457,8 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.pf = pf ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kD;
-    Tail want = want_of(ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
-                        h->P[ds].red, kTailGinSmall);
+    After want = after_of(ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
+                        h->P[ds].red, 3);
     GinSmallArgs& gsa = want.gs;
     gsa.D = h->P[ds];
     gsa.G = h->P[gs];
@@ -533,8 +501,8 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.partials = h->partials;
     a.pstride = h->pstride;
     a.extra = h->extra;
-    const Tail want = want_of(ranges(0, pf ? kG : 0), h->P[gs].red,
-                              kTailNone);
+    const After want = after_of(ranges(0, pf ? kG : 0), h->P[gs].red,
+                              0);
     rc = do_gin_pass(h, gs, a, want,
                      es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
                            (dyn.kind ? 2.0 * nG : 0.0)));
@@ -614,11 +582,9 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   h->extra = h->slot2 + tm + 1;
   h->pstride = h->extra + kNumExtra;
   int maxwg = 1;
-  const int fuse_env = env_int("HD_FUSE", 1);
   for (int s = 0; s < 2; ++s) {
     h->ld[s] = round_up(dims[s], kChunk);
     h->sh[s] = pick_shape(dims[s], h->ld[s]);
-    h->fuse[s] = fuse_env != 0;
     if (h->sh[s].nwg > maxwg) maxwg = h->sh[s].nwg;
   }
   int rc = HD_OK;
@@ -658,8 +624,6 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
       ALLOC(h->B[s], (size_t)h->es * (size_t)h->ld[s] * (size_t)tm);
   }
   ALLOC(h->flag, sizeof(int) * 4);
-  ALLOC(h->counter, sizeof(int) * (1 + kMaxGroups));
-  ALLOC(h->gpart, sizeof(double) * (size_t)kMaxGroups * h->pstride);
 #undef ALLOC
   for (int s = 0; s < 3; ++s) {
     double* p = s < 2 ? h->P[s].pi : h->gscal + 1;

@@ -4,9 +4,9 @@
 //    Box-Muller (1958) in FP64, keyed exactly as the library documents
 //    (key = (seed, trial), counter = (lo32(i/4), step, tag, hi32(i/4)));
 //  * 64-lane wavefront reductions, including a reduce-scatter that sums CG
-//    per-lane partials over the wave with 2*CG - 1 + log2(64/CG) shuffles
+//    per-lane partials over the wave with CG - 1 + log2(64/CG) shuffles
 //    instead of CG full reductions;
-//  * 4-element panel loads (one dwordx4 for FP32, two for FP64).
+//  * panel row loads (one 16-byte load per column for four FP32 rows).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -118,49 +118,9 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[CG]) {
   return r;
 }
 
-// Workgroup-wide column sums of CG per-thread partials; thread c < CG gets
-// column c's total in the return value (others get 0).  lds: kWaves*CG.
-template <int CG>
-__device__ __forceinline__ double block_column_sums(double (&v)[CG],
-                                                    double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int kGroup = 64 / CG;
-  const double r = wave_reduce_scatter<CG>(v);
-  if ((lane % kGroup) == 0) lds[wave * CG + lane / kGroup] = r;
-  __syncthreads();
-  double out = 0.0;
-  if (threadIdx.x < CG) {
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) out += lds[w * CG + threadIdx.x];
-  }
-  __syncthreads();
-  return out;
-}
-
-// ------------------------------------------------ cross-workgroup sums ---
-
-// Called by every thread of a workgroup after it has written its share of
-// some result: returns true in exactly one of the `expected` workgroups that
-// arrive at this counter, the last, after making the others' writes visible
-// to it; the counter is reset for the next launch.  Release/acquire is by
-// agent-scope fences around a relaxed atomic, so it also holds across XCDs.
-__device__ __forceinline__ bool arrive_last(int* counter, int expected) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int ticket = atomicAdd(counter, 1);
-    is_last = (ticket == expected - 1) ? 1 : 0;
-    if (is_last) *counter = 0;
-  }
-  __syncthreads();
-  const bool last = is_last != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 // out[slot] = sum_{w0 <= w < w1} P[w * pstride + slot] in increasing w, one
-// thread per slot; loads are issued eight rows at a time.
+// thread per slot; loads are issued eight rows at a time.  Ends with a
+// barrier.
 __device__ __forceinline__ void reduce_rows(const double* P, int pstride,
                                             int w0, int w1, SlotRanges rg,
                                             double* out) {
@@ -186,7 +146,6 @@ __device__ __forceinline__ void reduce_rows(const double* P, int pstride,
     for (; w < w1; ++w) acc += col[(int64_t)w * pstride];
     out[slot] = acc;
   }
-  __threadfence_block();
   __syncthreads();
 }
 

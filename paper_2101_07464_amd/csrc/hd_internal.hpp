@@ -89,27 +89,6 @@ struct GinSmallArgs {
   int* flag;
 };
 
-// What the last workgroup of a pass does after it has summed the partial
-// rows (when `counter` is set; otherwise the host launches k_reduce and the
-// small kernel separately).
-enum TailOp { kTailNone = 0, kTailSmallData = 1, kTailHaarSmall = 2,
-              kTailGinSmall = 3 };
-
-// The partial rows are summed by a two-level tree: the last workgroup of
-// each group of `gsz` consecutive workgroups sums its group's rows into
-// gpart, and the last of those sums the group rows into `out`.
-struct Tail {
-  int* counter;    // [0]: top level, [1 + g]: group g
-  double* gpart;   // one row of pstride doubles per group
-  int gsz;
-  SlotRanges rg;
-  double* out;
-  int op;
-  SmallDataArgs sd;
-  HaarSmallArgs hs;
-  GinSmallArgs gs;
-};
-
 // Element-wise map f_t fused into the random-side epilogue (kind 0: none).
 enum DynKind { kDynNone = 0, kDynTanh = 1, kDynSoftHist = 2, kDynNormalize = 3 };
 
@@ -144,7 +123,6 @@ struct TdotArgs {
   double* partials;
   int pstride;
   int extra;
-  Tail tail;
 };
 
 // One GEMV-N pass over a panel (columns 0..k-1) producing an output vector,
@@ -177,7 +155,6 @@ struct PassArgs {
   double* partials;
   int pstride;
   int extra;
-  Tail tail;
 };
 
 // Random-side pass of a Ginibre query (Algorithm 1).  With G the random side
@@ -210,7 +187,6 @@ struct GinPassArgs {
   double* partials;
   int pstride;
   int extra;
-  Tail tail;
 };
 
 struct DynArgs {
@@ -232,7 +208,43 @@ struct Shape {
   int nwg;
 };
 
+// Batched launches: many independent trials at the same query index share
+// one grid.  Block b works for trial blk_trial[b] as its block
+// b - blk_first[trial]; the per-trial arguments live in device memory and the
+// per-step fields (the same for every trial) come from StepPatch.
+struct StepPatch {
+  int k;            // reflectors per panel before this query
+  int kp;           // pending data column of the data side (or -1)
+  uint32_t step;    // 1-based query index
+  int pf;           // prefetch for step + 1
+  int want_ss;
+};
+
+struct BatchMap {
+  const int* blk_trial;
+  const int* blk_first;
+  int nblk;
+};
+
+// Per-trial epilogue of a batched pass, one workgroup per trial: the
+// fixed-order sums of the trial's partial rows, then an optional small step.
+enum TrialOp { kTrialReduce = 0, kTrialSmallData = 1, kTrialHaarSmall = 2 };
+
+struct TrialSums {
+  double* partials;
+  int pstride;
+  int nwg;
+  double* out;
+};
+
 int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s);
+int launch_tdot_batch(int f64, Shape sh, const TdotArgs* args, BatchMap bm,
+                      StepPatch p, int gen, hipStream_t s);
+int launch_pass_batch(int f64, Shape sh, int mode, const PassArgs* args,
+                      BatchMap bm, StepPatch p, hipStream_t s);
+int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
+                       SlotRanges rg, const SmallDataArgs* sd,
+                       const HaarSmallArgs* hs, StepPatch p, hipStream_t s);
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                 hipStream_t s);
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s);

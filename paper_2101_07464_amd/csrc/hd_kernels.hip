@@ -9,19 +9,19 @@
 // (the -sign(v1) factor of eq. (Householder) commutes with every later
 // reflector, so all of them collect into Delta).
 //
-// Panel kernels stream the panel once per pass, RPL rows per lane (4: one
-// 16-byte load per column for FP32; 1 for small panels, to give them more
-// workgroups), and keep every accumulation in FP64:
-//   k_tdot     : w = V' b (per-workgroup partials; column sums by a wave
-//                reduce-scatter, then LDS across the four waves)
-//   k_pass     : out = Delta a - V z (GEMV-N); writes the new panel column
-//                and the dot products with the next query's Philox draw
-//   k_gin_pass : the random side of a Ginibre query (two GEMV-N plus the
-//                explicit basis panel)
-// Cross-workgroup sums are fixed-order, so results are bitwise reproducible
-// run to run.  For small grids the last workgroup to finish does that sum and
-// the query's FP64 scalar step itself (Tail); otherwise k_reduce and a small
-// one-workgroup kernel follow.
+// Every panel kernel is one streaming sweep over its rows (RPL rows per lane:
+// 4 = one 16-byte load per column for FP32, 1 for small panels to give them
+// more workgroups) with all accumulation in FP64:
+//   tdot     : w = V' b (column dots), optionally a second right-hand side
+//   pass     : out = Delta a - V z (GEMV-N), the new panel column, and the dots
+//              of every column with the next query's Philox draw (prefetch)
+//   gin_pass : the random side of a Ginibre query (two GEMV-N plus the
+//              explicit basis panel)
+// Column dots are summed per wave with a barrier-free reduce-scatter into an
+// LDS window, per workgroup in fixed order, and across workgroups by k_reduce
+// (or k_trial_small for batches) in fixed order, so results are bitwise
+// reproducible run to run.  Small one-workgroup FP64 kernels update the WY
+// factor T and the reflector scalars.
 #include <hip/hip_runtime.h>
 
 #include "hd_device.hpp"
@@ -29,7 +29,11 @@
 
 namespace hd {
 
-constexpr int kCG = 16;  // columns per group in the panel loops
+constexpr int kFlush = 256;  // columns per LDS window of the column sums
+
+// Columns per group of the panel sweeps: each lane keeps one partial sum per
+// column of the group in registers (wider groups spill to scratch).
+constexpr int kCG = 16;
 
 // Draws g_step[i] for the RPL rows i0..i0+RPL-1 of one lane; rows outside
 // (lo, n) get 0.  Values are rounded to the storage type when `round`.
@@ -50,6 +54,86 @@ __device__ __forceinline__ void draw_rows(PhiloxKey key, uint32_t step,
   }
 }
 
+// One sweep over columns [0, nc) of a panel, over the rows of this workgroup
+// (CPT chunks of kWG * RPL rows starting at blk0):
+//   dots (ND = 1 or 2, when `dots`): d0[j] = sum_rows V[r, j] * rhs0[r]
+//        -> out0[j], and likewise rhs1 -> out1 (per-workgroup partials);
+//   GEMV-N (NZ = 0, 1 or 2): acc_q[r] -= zs_q * sum_j V[r, j] * z_q[j].
+template <typename T, int RPL, int CPT, int ND, int NZ>
+__device__ __forceinline__ void sweep(
+    const T* __restrict__ V, int64_t ld, int nc, int64_t blk0,
+    const bool (&cvalid)[CPT], const double (&rhs0)[CPT][RPL],
+    const double (&rhs1)[CPT][RPL], bool dots, const double* __restrict__ z0,
+    double zs0, const double* __restrict__ z1, double zs1,
+    double (&acc0)[CPT][RPL], double (&acc1)[CPT][RPL], double* wacc,
+    double* out0, double* out1) {
+  constexpr int CG = kCG;
+  constexpr int kRows = kWG * RPL;
+  constexpr int kGroup = 64 / CG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll 1
+  for (int w0 = 0; w0 < nc; w0 += kFlush) {
+    const int wend = min(nc, w0 + kFlush);
+#pragma unroll 1
+    for (int j0 = w0; j0 < wend; j0 += CG) {
+      double p0[CG], p1[ND == 2 ? CG : 1];
+      double q0[NZ >= 1 ? CG : 1], q1[NZ == 2 ? CG : 1];
+#pragma unroll
+      for (int jj = 0; jj < CG; ++jj) {
+        const bool ok = j0 + jj < nc;
+        p0[jj] = 0.0;
+        if constexpr (ND == 2) p1[jj] = 0.0;
+        if constexpr (NZ >= 1) q0[jj] = ok ? zs0 * z0[j0 + jj] : 0.0;
+        if constexpr (NZ == 2) q1[jj] = ok ? zs1 * z1[j0 + jj] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        if (!cvalid[c]) continue;
+        const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
+#pragma unroll
+        for (int jj = 0; jj < CG; ++jj) {
+          const int j = min(j0 + jj, nc - 1);
+          double v[RPL];
+          load_rows<RPL>(V + (int64_t)j * ld + r, v);
+#pragma unroll
+          for (int e = 0; e < RPL; ++e) {
+            if constexpr (NZ >= 1) acc0[c][e] -= v[e] * q0[jj];
+            if constexpr (NZ == 2) acc1[c][e] -= v[e] * q1[jj];
+            if constexpr (ND >= 1) p0[jj] += v[e] * rhs0[c][e];
+            if constexpr (ND == 2) p1[jj] += v[e] * rhs1[c][e];
+          }
+        }
+      }
+      if constexpr (ND >= 1) {
+        if (dots) {
+          const int col = j0 + lane / kGroup;
+          const bool owner = (lane % kGroup) == 0 && col < wend;
+          const double s0 = wave_reduce_scatter<CG>(p0);
+          if (owner) wacc[wave * kFlush + (col - w0)] = s0;
+          if constexpr (ND == 2) {
+            const double s1 = wave_reduce_scatter<CG>(p1);
+            if (owner) wacc[(kWaves + wave) * kFlush + (col - w0)] = s1;
+          }
+        }
+      }
+    }
+    if (ND >= 1 && dots) {
+      __syncthreads();
+      for (int jj = tid; jj < wend - w0; jj += kWG) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          s0 += wacc[w * kFlush + jj];
+          if (ND == 2) s1 += wacc[(kWaves + w) * kFlush + jj];
+        }
+        out0[w0 + jj] = s0;
+        if (ND == 2) out1[w0 + jj] = s1;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------- small FP64 steps ------
 
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
@@ -64,7 +148,6 @@ __device__ void small_data_body(const SmallDataArgs& a) {
       a.T[j + (int64_t)kp * tm] = -tau * s;
     }
   }
-  __threadfence_block();
   __syncthreads();
   if (a.w) {
     for (int j = threadIdx.x; j < a.k; j += kWG) {
@@ -142,7 +225,6 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
     sh[2] = gk;
     sh[3] = upG;
   }
-  __threadfence_block();
   __syncthreads();
   const double tauG = sh[0], cs = sh[1], gk = sh[2], upG = sh[3];
   const double piGk = a.G.pi[k];
@@ -155,7 +237,6 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
     cG[j] = gdot + (double)colG[k] * upG;
     sv[j] = hg + piGk * cs * (gdot + (double)colG[k] * gk);
   }
-  __threadfence_block();
   __syncthreads();
   for (int j = tid; j < k; j += kWG) {
     double tG = 0.0, zz = 0.0;
@@ -187,7 +268,6 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
     a.scal[0] = nu;
     sh[0] = nu;
   }
-  __threadfence_block();
   __syncthreads();
   const double nu = sh[0];
   const double pil = a.G.pi[l];
@@ -199,7 +279,6 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
     s1[j] = v1;
     s2[j] = hs + nu * v1;
   }
-  __threadfence_block();
   __syncthreads();
   for (int j = tid; j < l; j += kWG) {
     double z1 = 0.0, z2 = 0.0;
@@ -213,34 +292,6 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   }
 }
 
-// Last-workgroup epilogue of a panel kernel: sum the partial rows in a fixed
-// order, then run the query's small step.  A no-op without a counter.
-template <typename T>
-__device__ __forceinline__ void run_tail(const Tail& tl,
-                                         const double* partials, int pstride) {
-  if (!tl.counter) return;
-  const int nwg = gridDim.x;
-  const int g = blockIdx.x / tl.gsz;
-  const int ng = (nwg + tl.gsz - 1) / tl.gsz;
-  const int w0 = g * tl.gsz, w1 = min(w0 + tl.gsz, nwg);
-  if (!arrive_last(tl.counter + 1 + g, w1 - w0)) return;
-  if (ng == 1) {
-    reduce_rows(partials, pstride, w0, w1, tl.rg, tl.out);
-  } else {
-    reduce_rows(partials, pstride, w0, w1, tl.rg,
-                tl.gpart + (int64_t)g * pstride);
-    if (!arrive_last(tl.counter, ng)) return;
-    reduce_rows(tl.gpart, pstride, 0, ng, tl.rg, tl.out);
-  }
-  __threadfence();
-  if (tl.op == kTailSmallData)
-    small_data_body(tl.sd);
-  else if (tl.op == kTailHaarSmall)
-    haar_small_body<T>(tl.hs);
-  else if (tl.op == kTailGinSmall)
-    gin_small_body<T>(tl.gs);
-}
-
 // Element-wise map f_t on one row (y already rounded to storage).
 __device__ __forceinline__ double dyn_row(const DynFuse& d, double yi,
                                           double xi, double xpi) {
@@ -252,14 +303,13 @@ __device__ __forceinline__ double dyn_row(const DynFuse& d, double yi,
 // ------------------------------------------------------------------ TDOT --
 
 template <typename T, int RPL, int CPT, bool GEN, bool TWO>
-__global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
+__device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
   constexpr int kRows = kWG * RPL;
-  __shared__ double lds[kWaves * kCG];
+  __shared__ double wacc[2 * kWaves * kFlush];
   __shared__ double scr[kWaves];
   const int tid = threadIdx.x;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
-  double b[CPT][RPL];
-  double b2[CPT][RPL];
+  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
+  double rhs[2][CPT][RPL];
   bool cvalid[CPT];
   double ss = 0.0;
   const PhiloxKey key{a.key.k0, a.key.k1};
@@ -268,74 +318,45 @@ __global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
     const int64_t row0 = blk0 + (int64_t)c * kRows;
     cvalid[c] = row0 < a.ld;
     const int64_t i0 = row0 + RPL * tid;
-    if (GEN) {
+    if (GEN)
       draw_rows<T, RPL>(key, a.gen_step, i0, a.lo, cvalid[c] ? a.n : 0, true,
-                        b[c]);
-    }
+                        rhs[0][c]);
 #pragma unroll
     for (int e = 0; e < RPL; ++e) {
       const int64_t i = i0 + e;
       const bool in = cvalid[c] && i < a.n;
-      if (!GEN) b[c][e] = (in && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
-      b2[c][e] = (TWO && in) ? (double)((const T*)a.b2)[i] : 0.0;
-      ss += b[c][e] * b[c][e];
+      if (!GEN)
+        rhs[0][c][e] = (in && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
+      rhs[1][c][e] = (TWO && in) ? (double)((const T*)a.b2)[i] : 0.0;
+      ss += rhs[0][c][e] * rhs[0][c][e];
     }
   }
-  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
-#pragma unroll 1
-  for (int seg = 0; seg < 2; ++seg) {
-    const T* V = (const T*)(seg ? a.V2 : a.V);
-    const int nc = seg ? a.ncols2 : a.ncols;
-    const int slot0 = seg ? a.ncols : 0;
-#pragma unroll 1
-    for (int j0 = 0; j0 < nc; j0 += kCG) {
-      double acc[kCG], acc2[kCG];
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        acc[jj] = 0.0;
-        acc2[jj] = 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        if (!cvalid[c]) continue;
-        const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
-#pragma unroll
-        for (int jj = 0; jj < kCG; ++jj) {
-          const int j = min(j0 + jj, nc - 1);
-          double v[RPL];
-          load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
-#pragma unroll
-          for (int e = 0; e < RPL; ++e) {
-            acc[jj] += v[e] * b[c][e];
-            if (TWO) acc2[jj] += v[e] * b2[c][e];
-          }
-        }
-      }
-      const double s = block_column_sums<kCG>(acc, lds);
-      if (tid < kCG && j0 + tid < nc) out[slot0 + j0 + tid] = s;
-      if (TWO && seg == 0) {
-        const double s2 = block_column_sums<kCG>(acc2, lds);
-        if (tid < kCG && j0 + tid < nc) out[a.slot2 + j0 + tid] = s2;
-      }
-    }
-  }
+  double* out = a.partials + (int64_t)blk * a.pstride;
+  double acc[CPT][RPL];
+  sweep<T, RPL, CPT, TWO ? 2 : 1, 0>((const T*)a.V, a.ld, a.ncols, blk0,
+                                     cvalid, rhs[0], rhs[1], true, nullptr,
+                                     0.0, nullptr, 0.0, acc, acc, wacc, out,
+                                     out + a.slot2);
+  if (a.ncols2 > 0)
+    sweep<T, RPL, CPT, 1, 0>((const T*)a.V2, a.ld, a.ncols2, blk0, cvalid,
+                             rhs[0], rhs[1], true, nullptr, 0.0, nullptr, 0.0,
+                             acc, acc, wacc, out + a.ncols, nullptr);
   if (a.want_ss) {
     const double s = block_sum(ss, scr);
     if (tid == 0) out[a.extra + kSlotPFSS] = s;
   }
-  run_tail<T>(a.tail, a.partials, a.pstride);
 }
 
 // ---------------------------------------------------------------- GEMV-N --
 
 template <typename T, int RPL, int CPT, int MODE>
-__global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
   constexpr int kRows = kWG * RPL;
-  __shared__ double lds[kWaves * kCG];
+  __shared__ double wacc[kWaves * kFlush];
   __shared__ double scr[kWaves];
   const int tid = threadIdx.x;
   const int k = a.k;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
+  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
   T* __restrict__ V = (T*)a.V;
   const PhiloxKey key{a.key.k0, a.key.k1};
   double acc[CPT][RPL];
@@ -354,38 +375,9 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
       pfss += gn[c][e] * gn[c][e];
     }
   }
-  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
-
-#pragma unroll 1
-  for (int j0 = 0; j0 < k; j0 += kCG) {
-    double zz[kCG];
-    double pacc[kCG];
-#pragma unroll
-    for (int jj = 0; jj < kCG; ++jj) {
-      zz[jj] = (j0 + jj < k) ? a.z[j0 + jj] : 0.0;
-      pacc[jj] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        const int j = min(j0 + jj, k - 1);
-        double v[RPL];
-        load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) {
-          acc[c][e] -= v[e] * zz[jj];
-          pacc[jj] += v[e] * gn[c][e];
-        }
-      }
-    }
-    if (a.pf) {
-      const double s = block_column_sums<kCG>(pacc, lds);
-      if (tid < kCG && j0 + tid < k) out[j0 + tid] = s;
-    }
-  }
+  double* out = a.partials + (int64_t)blk * a.pstride;
+  sweep<T, RPL, CPT, 1, 1>(V, a.ld, k, blk0, cvalid, gn, gn, a.pf != 0, a.z,
+                           1.0, nullptr, 0.0, acc, acc, wacc, out, nullptr);
 
   // Epilogue: form the output rows, write the new column k, and the extras.
   double ssq = 0.0, pfnew = 0.0, ysq = 0.0;
@@ -451,22 +443,20 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
       out[a.extra + kSlotPFSS] = s2;
     }
   }
-  run_tail<T>(a.tail, a.partials, a.pstride);
 }
 
 // ------------------------------------------------- Ginibre random side --
 
 template <typename T, int RPL, int CPT>
-__global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
+__device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   constexpr int kRows = kWG * RPL;
-  __shared__ double lds[kWaves * kCG];
+  __shared__ double wacc[kWaves * kFlush];
   const int tid = threadIdx.x;
   const int k = a.k, nb = a.nb;
-  const int64_t blk0 = (int64_t)blockIdx.x * (kRows * CPT);
-  const T* __restrict__ V = (const T*)a.V;
+  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
   T* __restrict__ B = (T*)a.B;
   const PhiloxKey key{a.key.k0, a.key.k1};
-  double acc1[CPT][RPL], acc2[CPT][RPL], gn[CPT][RPL];
+  double acc0[CPT][RPL], acc1[CPT][RPL], gn[CPT][RPL];
   bool cvalid[CPT];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
@@ -476,66 +466,21 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
                       (a.pf && cvalid[c]) ? a.n : 0, true, gn[c]);
 #pragma unroll
     for (int e = 0; e < RPL; ++e) {
+      acc0[c][e] = 0.0;
       acc1[c][e] = 0.0;
-      acc2[c][e] = 0.0;
     }
   }
-  double* out = a.partials + (int64_t)blockIdx.x * a.pstride;
-  // reflector panel: two GEMV-N (z1 -> new basis vector, z2 -> output) and
-  // the prefetch dots
-#pragma unroll 1
-  for (int j0 = 0; j0 < k; j0 += kCG) {
-    double za[kCG], zb[kCG], pacc[kCG];
-#pragma unroll
-    for (int jj = 0; jj < kCG; ++jj) {
-      const bool ok = j0 + jj < k;
-      za[jj] = ok ? a.z1[j0 + jj] : 0.0;
-      zb[jj] = ok ? a.z2[j0 + jj] : 0.0;
-      pacc[jj] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        const int j = min(j0 + jj, k - 1);
-        double v[RPL];
-        load_rows<RPL>(V + (int64_t)j * a.ld + r, v);
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) {
-          acc1[c][e] -= v[e] * za[jj];
-          acc2[c][e] -= v[e] * zb[jj];
-          pacc[jj] += v[e] * gn[c][e];
-        }
-      }
-    }
-    if (a.pf) {
-      const double s = block_column_sums<kCG>(pacc, lds);
-      if (tid < kCG && j0 + tid < k) out[j0 + tid] = s;
-    }
-  }
-  // explicit basis panel: + B c
-#pragma unroll 1
-  for (int j0 = 0; j0 < nb; j0 += kCG) {
-    double cv[kCG];
-#pragma unroll
-    for (int jj = 0; jj < kCG; ++jj)
-      cv[jj] = (j0 + jj < nb) ? a.c[j0 + jj] : 0.0;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      if (!cvalid[c]) continue;
-      const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
-#pragma unroll
-      for (int jj = 0; jj < kCG; ++jj) {
-        const int j = min(j0 + jj, nb - 1);
-        double v[RPL];
-        load_rows<RPL>(B + (int64_t)j * a.ld + r, v);
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) acc2[c][e] += v[e] * cv[jj];
-      }
-    }
-  }
+  double* out = a.partials + (int64_t)blk * a.pstride;
+  // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
+  // and the prefetch dots
+  sweep<T, RPL, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, cvalid, gn, gn,
+                           a.pf != 0, a.z1, 1.0, a.z2, 1.0, acc0, acc1, wacc,
+                           out, nullptr);
+  // explicit basis panel: acc1 += B c
+  if (nb > 0)
+    sweep<T, RPL, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, cvalid, gn, gn,
+                             false, a.c, -1.0, nullptr, 0.0, acc1, acc1, wacc,
+                             nullptr, nullptr);
   const double nu = a.scal[0], sigma = a.scal[1];
   const double pik = a.pi[k];
 #pragma unroll
@@ -550,9 +495,9 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
       if (i >= a.n) continue;
       const double sg = (i < k) ? a.pi[i + 1] : pik;
       const double gi = gt[e];
-      B[(int64_t)nb * a.ld + i] = (T)(sg * gi + acc1[c][e]);
+      B[(int64_t)nb * a.ld + i] = (T)(sg * gi + acc0[c][e]);
       const double hv = (i < k) ? a.h[i] : 0.0;
-      const T ys = (T)(sigma * (acc2[c][e] + sg * (hv + nu * gi)));
+      const T ys = (T)(sigma * (acc1[c][e] + sg * (hv + nu * gi)));
       ((T*)a.y)[i] = ys;
       if (a.dyn.kind) {
         const double xi = (double)((const T*)a.dyn.x)[i];
@@ -563,7 +508,94 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
       }
     }
   }
-  run_tail<T>(a.tail, a.partials, a.pstride);
+}
+
+// ---------------------------------------------------- kernel wrappers ----
+
+template <typename T, int RPL, int CPT, bool GEN, bool TWO>
+__global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
+  tdot_body<T, RPL, CPT, GEN, TWO>(a, blockIdx.x);
+}
+
+template <typename T, int RPL, int CPT, int MODE>
+__global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
+  pass_body<T, RPL, CPT, MODE>(a, blockIdx.x);
+}
+
+template <typename T, int RPL, int CPT>
+__global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
+  gin_pass_body<T, RPL, CPT>(a, blockIdx.x);
+}
+
+// Ring of three trajectory vectors of a batched trial, stride ld: x_t is
+// slot (t-1) % 3.
+template <typename T>
+__device__ __forceinline__ const T* ring_slot(const void* base, int64_t ld,
+                                              int slot) {
+  return (const T*)base + (int64_t)slot * ld;
+}
+
+template <typename T, int RPL, int CPT, bool GEN, bool TWO>
+__global__ __launch_bounds__(kWG) void k_tdot_batch(const TdotArgs* A,
+                                                    BatchMap bm, StepPatch p) {
+  const int trial = bm.blk_trial[blockIdx.x];
+  TdotArgs a = A[trial];
+  a.ncols = p.k;
+  if (GEN) {
+    a.gen_step = p.step;
+    a.lo = p.k;
+    a.want_ss = p.want_ss;
+  } else {
+    a.b = ring_slot<T>(a.b, a.ld, (int)((p.step - 1) % 3));
+    a.b2 = TWO ? (const void*)((const T*)a.V + (int64_t)p.kp * a.ld) : nullptr;
+  }
+  tdot_body<T, RPL, CPT, GEN, TWO>(a, blockIdx.x - bm.blk_first[trial]);
+}
+
+template <typename T, int RPL, int CPT, int MODE>
+__global__ __launch_bounds__(kWG) void k_pass_batch(const PassArgs* A,
+                                                    BatchMap bm, StepPatch p) {
+  const int trial = bm.blk_trial[blockIdx.x];
+  PassArgs a = A[trial];
+  a.k = p.k;
+  a.step = p.step;
+  a.pf = p.pf;
+  a.pf_step = p.step + 1;
+  a.pf_cut = p.k + 1;
+  if (MODE == kPassData) a.x = ring_slot<T>(a.x, a.ld, (int)((p.step - 1) % 3));
+  if (a.dyn.kind) {
+    // dyn.x holds the ring base: x_t, x_{t-1}, x_{t+1} are its slots
+    const void* ring = a.dyn.x;
+    a.dyn.x = ring_slot<T>(ring, a.ld, (int)((p.step - 1) % 3));
+    a.dyn.xprev = ring_slot<T>(ring, a.ld, (int)((p.step + 1) % 3));
+    a.dyn.xnext = (void*)ring_slot<T>(ring, a.ld, (int)(p.step % 3));
+  }
+  pass_body<T, RPL, CPT, MODE>(a, blockIdx.x - bm.blk_first[trial]);
+}
+
+// One workgroup per trial: fixed-order sums of the trial's partial rows,
+// then the trial's small FP64 step.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_trial_small(int op,
+                                                     const TrialSums* sums,
+                                                     SlotRanges rg,
+                                                     const SmallDataArgs* sd,
+                                                     const HaarSmallArgs* hs,
+                                                     StepPatch p) {
+  const int trial = blockIdx.x;
+  const TrialSums S = sums[trial];
+  reduce_rows(S.partials, S.pstride, 0, S.nwg, rg, S.out);
+  if (op == kTrialSmallData) {
+    SmallDataArgs a = sd[trial];
+    a.kp = p.kp;
+    a.k = p.k;
+    small_data_body(a);
+  } else if (op == kTrialHaarSmall) {
+    HaarSmallArgs a = hs[trial];
+    a.k = p.k;
+    a.step = p.step;
+    haar_small_body<T>(a);
+  }
 }
 
 // ------------------------------------------------- standalone kernels ----
@@ -648,21 +680,27 @@ __global__ __launch_bounds__(kWG) void k_fill(double* p, double v,
   } while (0)
 
 // Launch shapes (rpl, cpt): (1,1) for small panels, (4, 1|2|4|8) otherwise.
+#define HD_DISPATCH_SHAPE(SH, KERNEL_T, ...)                                 \
+  do {                                                                       \
+    if ((SH).rpl == 1 && (SH).cpt == 1)                                      \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(1, 1)), __VA_ARGS__);      \
+    else if ((SH).rpl == 4 && (SH).cpt == 1)                                 \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 1)), __VA_ARGS__);      \
+    else if ((SH).rpl == 4 && (SH).cpt == 2)                                 \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 2)), __VA_ARGS__);      \
+    else if ((SH).rpl == 4 && (SH).cpt == 4)                                 \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 4)), __VA_ARGS__);      \
+    else if ((SH).rpl == 4 && (SH).cpt == 8)                                 \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 8)), __VA_ARGS__);      \
+    else                                                                     \
+      return -1;                                                             \
+  } while (0)
+
 template <typename T, bool GEN, bool TWO>
 static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s) {
-  const dim3 g(sh.nwg), b(kWG);
-  if (sh.rpl == 1 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 1, 1, GEN, TWO>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 1, GEN, TWO>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 2)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 2, GEN, TWO>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 4)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 4, GEN, TWO>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 8)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_tdot<T, 4, 8, GEN, TWO>), g, b, 0, s, a);
-  else
-    return -1;
+#define K_(R, C) k_tdot<T, R, C, GEN, TWO>
+  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+#undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -678,21 +716,36 @@ int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s) {
   return f64 ? tdot_t<double>(sh, a, s) : tdot_t<float>(sh, a, s);
 }
 
+template <typename T, bool GEN, bool TWO>
+static int tdot_batch_shape(Shape sh, const TdotArgs* A, BatchMap bm,
+                            StepPatch p, hipStream_t s) {
+#define K_(R, C) k_tdot_batch<T, R, C, GEN, TWO>
+  HD_DISPATCH_SHAPE(sh, K_, dim3(bm.nblk), dim3(kWG), 0, s, A, bm, p);
+#undef K_
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+template <typename T>
+static int tdot_batch_t(Shape sh, const TdotArgs* A, BatchMap bm, StepPatch p,
+                        int gen, hipStream_t s) {
+  if (gen) return tdot_batch_shape<T, true, false>(sh, A, bm, p, s);
+  if (p.kp > 0) return tdot_batch_shape<T, false, true>(sh, A, bm, p, s);
+  return tdot_batch_shape<T, false, false>(sh, A, bm, p, s);
+}
+
+int launch_tdot_batch(int f64, Shape sh, const TdotArgs* args, BatchMap bm,
+                      StepPatch p, int gen, hipStream_t s) {
+  if (bm.nblk <= 0) return 0;
+  return f64 ? tdot_batch_t<double>(sh, args, bm, p, gen, s)
+             : tdot_batch_t<float>(sh, args, bm, p, gen, s);
+}
+
 template <typename T, int MODE>
 static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s) {
-  const dim3 g(sh.nwg), b(kWG);
-  if (sh.rpl == 1 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 1, 1, MODE>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 1, MODE>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 2)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 2, MODE>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 4)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 4, MODE>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 8)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pass<T, 4, 8, MODE>), g, b, 0, s, a);
-  else
-    return -1;
+#define K_(R, C) k_pass<T, R, C, MODE>
+  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+#undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -706,27 +759,53 @@ int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                            : pass_shape<float, kPassRandHaar>(sh, a, s);
 }
 
+template <typename T, int MODE>
+static int pass_batch_shape(Shape sh, const PassArgs* A, BatchMap bm,
+                            StepPatch p, hipStream_t s) {
+#define K_(R, C) k_pass_batch<T, R, C, MODE>
+  HD_DISPATCH_SHAPE(sh, K_, dim3(bm.nblk), dim3(kWG), 0, s, A, bm, p);
+#undef K_
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_pass_batch(int f64, Shape sh, int mode, const PassArgs* args,
+                      BatchMap bm, StepPatch p, hipStream_t s) {
+  if (bm.nblk <= 0) return 0;
+  if (f64)
+    return mode == kPassData
+               ? pass_batch_shape<double, kPassData>(sh, args, bm, p, s)
+               : pass_batch_shape<double, kPassRandHaar>(sh, args, bm, p, s);
+  return mode == kPassData
+             ? pass_batch_shape<float, kPassData>(sh, args, bm, p, s)
+             : pass_batch_shape<float, kPassRandHaar>(sh, args, bm, p, s);
+}
+
 template <typename T>
 static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
-  const dim3 g(sh.nwg), b(kWG);
-  if (sh.rpl == 1 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 1, 1>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 1)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 1>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 2)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 2>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 4)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 4>), g, b, 0, s, a);
-  else if (sh.rpl == 4 && sh.cpt == 8)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gin_pass<T, 4, 8>), g, b, 0, s, a);
-  else
-    return -1;
+#define K_(R, C) k_gin_pass<T, R, C>
+  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+#undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s) {
   return f64 ? gin_shape<double>(sh, a, s) : gin_shape<float>(sh, a, s);
+}
+
+int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
+                       SlotRanges rg, const SmallDataArgs* sd,
+                       const HaarSmallArgs* hs, StepPatch p, hipStream_t s) {
+  if (ntrials <= 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<double>), dim3(ntrials),
+                       dim3(kWG), 0, s, op, sums, rg, sd, hs, p);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<float>), dim3(ntrials),
+                       dim3(kWG), 0, s, op, sums, rg, sd, hs, p);
+  HD_CHECK_LAUNCH();
+  return 0;
 }
 
 int launch_reduce(const double* partials, int pstride, int nwg,
