@@ -4,8 +4,8 @@
 //    Box-Muller (1958) in FP64, keyed exactly as the library documents
 //    (key = (seed, trial), counter = (lo32(i/4), step, tag, hi32(i/4)));
 //  * 64-lane wavefront reductions, including a reduce-scatter that sums CG
-//    per-lane partials over the wave with CG - 1 + log2(64/CG) shuffles
-//    instead of CG full reductions;
+//    per-lane partials over the wave with CG - 1 + log2(64/CG) exchanges
+//    instead of CG full reductions, on permlane swaps and DPP moves (no LDS);
 //  * panel row loads (one 16-byte load per column for four FP32 rows).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -93,29 +93,116 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return r;
 }
 
+// ------------------------------------------- cross-lane exchanges ------
+//
+// The reduce-scatter below pairs lane l with a partner whose lane bit OFF
+// differs and whose higher bits agree: OFF = 32 and 16 use the gfx950
+// permlane swaps (one instruction exchanges the halves of two registers),
+// OFF = 8, 4, 2, 1 use DPP moves (row_ror:8, row_half_mirror, and two quad
+// permutations).  Partners are l ^ OFF except at OFF = 4, where row_half_mirror
+// pairs l with the lane 7 - (l & 7) of the same group of eight; that lane also
+// differs in bit 4 and agrees above it, which is all the reduction needs.
+
+__device__ __forceinline__ uint32_t lo_word(double v) {
+  return (uint32_t)__builtin_bit_cast(uint64_t, v);
+}
+__device__ __forceinline__ uint32_t hi_word(double v) {
+  return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 32);
+}
+__device__ __forceinline__ double from_words(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int OFF>
+constexpr int dpp_ctrl() {
+  return OFF == 8 ? 0x128 : OFF == 4 ? 0x141 : OFF == 2 ? 0x4E : 0xB1;
+}
+
+// v from the partner lane (OFF = 8, 4, 2, 1).
+template <int OFF>
+__device__ __forceinline__ double dpp_partner(double v) {
+  static_assert(OFF == 8 || OFF == 4 || OFF == 2 || OFF == 1, "OFF");
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)lo_word(v), dpp_ctrl<OFF>(),
+                                             0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)hi_word(v), dpp_ctrl<OFF>(),
+                                             0xF, 0xF, true);
+  return from_words((uint32_t)lo, (uint32_t)hi);
+}
+
+// Sum of v and the partner lane's v.
+template <int OFF>
+__device__ __forceinline__ double add_partner(double v) {
+  if constexpr (OFF >= 16)
+    return v + __shfl_xor(v, OFF, 64);
+  else
+    return v + dpp_partner<OFF>(v);
+}
+
+// One level of the wave reduce-scatter: lanes with the OFF bit set keep the
+// upper H partial sums, the others the lower H, and each adds its partner's
+// copy of the half it keeps.  Levels are compile-time so that every array
+// index is a constant.
+template <int H, int OFF, int CG>
+__device__ __forceinline__ void rs_level(double (&v)[CG], bool upper) {
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    if constexpr (OFF == 32 || OFF == 16) {
+      // permlane{32,16}_swap exchange the odd rows (of OFF lanes) of the
+      // first operand with the even rows of the second: afterwards lanes
+      // of even rows hold (own v[q], partner v[q]) and lanes of odd rows
+      // (partner v[q+H], own v[q+H]).
+      const double a = v[q], b = v[q + H];
+      uint32_t l0, l1, h0, h1;
+      if constexpr (OFF == 32) {
+        const auto L = __builtin_amdgcn_permlane32_swap(lo_word(a), lo_word(b),
+                                                        false, false);
+        const auto U = __builtin_amdgcn_permlane32_swap(hi_word(a), hi_word(b),
+                                                        false, false);
+        l0 = L[0]; l1 = L[1]; h0 = U[0]; h1 = U[1];
+      } else {
+        const auto L = __builtin_amdgcn_permlane16_swap(lo_word(a), lo_word(b),
+                                                        false, false);
+        const auto U = __builtin_amdgcn_permlane16_swap(hi_word(a), hi_word(b),
+                                                        false, false);
+        l0 = L[0]; l1 = L[1]; h0 = U[0]; h1 = U[1];
+      }
+      // even rows: own + partner; odd rows: partner + own (the same sum)
+      const double x = from_words(l0, h0), y = from_words(l1, h1);
+      v[q] = x + y;
+    } else {
+      const double send = upper ? v[q] : v[q + H];
+      const double keep = upper ? v[q + H] : v[q];
+      v[q] = keep + dpp_partner<OFF>(send);
+    }
+  }
+}
+
+template <int H, int OFF, int CG>
+__device__ __forceinline__ void rs_levels(double (&v)[CG], int lane) {
+  if constexpr (H >= 1) {
+    rs_level<H, OFF, CG>(v, (lane & OFF) != 0);
+    rs_levels<H / 2, OFF / 2, CG>(v, lane);
+  }
+}
+
+template <int OFF>
+__device__ __forceinline__ double rs_tail(double r) {
+  if constexpr (OFF >= 1)
+    return rs_tail<OFF / 2>(add_partner<OFF>(r));
+  else
+    return r;
+}
+
 // Reduce-scatter over one wave: each lane holds CG partial sums v[0..CG-1]
 // (one per column).  On return, lanes with lane % (64/CG) == 0 hold in the
 // result the wave total of column lane / (64/CG).  CG must be a power of two
 // no larger than 64.  v is clobbered.
 template <int CG>
 __device__ __forceinline__ double wave_reduce_scatter(double (&v)[CG]) {
+  static_assert(CG >= 1 && CG <= 64 && (CG & (CG - 1)) == 0, "CG");
   const int lane = threadIdx.x & 63;
-  int off = 32;
-#pragma unroll
-  for (int h = CG / 2; h >= 1; h >>= 1) {
-    const bool upper = (lane & off) != 0;
-#pragma unroll
-    for (int q = 0; q < h; ++q) {
-      const double send = upper ? v[q] : v[q + h];
-      const double keep = upper ? v[q + h] : v[q];
-      v[q] = keep + __shfl_xor(send, off, 64);
-    }
-    off >>= 1;
-  }
-  double r = v[0];
-#pragma unroll
-  for (int o = 32 / CG; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-  return r;
+  rs_levels<CG / 2, 32, CG>(v, lane);
+  return rs_tail<32 / CG>(v[0]);
 }
 
 // out[slot] = sum_{w0 <= w < w1} P[w * pstride + slot] in increasing w, one
