@@ -37,7 +37,11 @@ struct hd_ctx {
   PanelDev P[2];   // 0 = R (acts on R^n), 1 = L (acts on R^m)
   int pf_step[2];  // query index whose random-side prefetch P[s].red holds
   int pending[2];  // data column whose T column still needs V'u, or -1
+  int hint;        // transpose flag of the next query: -1 unknown, 0 or 1,
+                   // kHintNone when no query is expected to follow
   double* partials;
+  double* partials2;  // partial rows of the random-side pass
+  ReduceJob deferred; // its sums, launched with the next reduction
   double* w;       // TDOT results (pstride)
   double* zD;      // T' w (t_max)
   double* zG;      // random-side coefficients + scratch (3 t_max)
@@ -61,6 +65,8 @@ struct hd_ctx {
 };
 
 namespace {
+
+constexpr int kHintNone = 2;
 
 thread_local char g_err[256];
 
@@ -201,6 +207,7 @@ PassArgs pass_base(hd_ctx* h, int side) {
   a.pstride = h->pstride;
   a.extra = h->extra;
   a.key = Key{h->cfg.seed, h->cfg.trial};
+  a.cslot = -1;
   return a;
 }
 
@@ -238,9 +245,21 @@ After after_of(SlotRanges rg, double* out, int op) {
   return t;
 }
 
+ReduceJob no_job() {
+  ReduceJob j;
+  std::memset(&j, 0, sizeof(j));
+  return j;
+}
+
 int run_after(hd_ctx* h, int side, const After& af) {
-  LCHK(launch_reduce(h->partials, h->pstride, h->sh[side].nwg, af.rg, af.out,
-                     h->stream));
+  ReduceJob ja;
+  ja.P = h->partials;
+  ja.pstride = h->pstride;
+  ja.nwg = h->sh[side].nwg;
+  ja.rg = af.rg;
+  ja.out = af.out;
+  LCHK(launch_reduce(ja, h->deferred, h->stream));
+  h->deferred = no_job();
   if (af.op == 1) LCHK(launch_small_data(af.sd, h->stream));
   if (af.op == 2) LCHK(launch_haar_small(h->f64, af.hs, h->stream));
   if (af.op == 3) LCHK(launch_gin_small(h->f64, af.gs, h->stream));
@@ -265,13 +284,40 @@ int do_pass(hd_ctx* h, int side, int mode, const PassArgs& a,
   return run_after(h, side, af);
 }
 
-int do_gin_pass(hd_ctx* h, int side, const GinPassArgs& a, const After& af,
-                double bytes) {
-  {
-    ProfScope ps(h, 2, bytes);
-    LCHK(launch_gin_pass(h->f64, h->sh[side], a, h->stream));
+// The random-side pass ends a query.  Its partial rows (in partials2) are
+// summed by the next reduction launch, which always precedes the next read
+// of P[side].red.
+void defer_after(hd_ctx* h, int side, const After& af) {
+  h->deferred.P = h->partials2;
+  h->deferred.pstride = h->pstride;
+  h->deferred.nwg = h->sh[side].nwg;
+  h->deferred.rg = af.rg;
+  h->deferred.out = af.out;
+}
+
+// Which of this query's by-products the next one uses.  pf_data: the data
+// pass's dots of its panel with the next draw (the data side is the next
+// random side); pf_rand: likewise for the random pass; tcol: the data side's
+// new T column is formed now (in the data pass) rather than by a later pass.
+struct Plan {
+  bool pf_data, pf_rand, tcol;
+};
+
+Plan plan_of(const hd_ctx* h, int ds, int step) {
+  Plan p;
+  const bool room = step + 1 <= h->cfg.t_max;
+  if (h->hint == kHintNone) {
+    p.pf_data = p.pf_rand = p.tcol = false;
+  } else if (h->hint < 0) {
+    p.pf_data = p.pf_rand = room;
+    p.tcol = false;
+  } else {
+    const int next_gs = 1 - (h->hint ? 1 : 0);
+    p.pf_data = room && next_gs == ds;
+    p.pf_rand = room && next_gs != ds;
+    p.tcol = next_gs == ds;
   }
-  return run_after(h, side, af);
+  return p;
 }
 
 const void* panel_col(hd_ctx* h, int side, int j) {
@@ -356,7 +402,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     rc = prefetch(h, gs, k, step, k, 1);
     if (rc) return rc;
   }
-  const bool pf = step + 1 <= h->cfg.t_max;
+  const Plan pl = plan_of(h, ds, step);
   rc = data_tdot(h, ds, x, k, 0);
   if (rc) return rc;
   // p = Delta_D (x - V_D z_D); new column k of V_D; prefetch for step+1;
@@ -368,11 +414,13 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.x = x;
     a.head = h->head;
     a.pivot = h->scal;
-    a.pf = pf ? 1 : 0;
+    a.pf = pl.pf_data ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    After want = after_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                        h->P[ds].red, 2);
+    a.cslot = pl.tcol && k > 0 ? h->slot2 : -1;
+    After want = after_of(ranges(0, pl.pf_data ? k + 1 : 0, h->slot2,
+                                 a.cslot >= 0 ? k : 0, h->extra, kNumExtra),
+                          h->P[ds].red, 2);
     HaarSmallArgs& hs = want.hs;
     hs.D = h->P[ds];
     hs.G = h->P[gs];
@@ -385,6 +433,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     hs.key = Key{h->cfg.seed, h->cfg.trial};
     hs.step = (uint32_t)step;
     hs.extra = h->extra;
+    hs.cslot = a.cslot;
     hs.flag = h->flag;
     rc = do_pass(h, ds, kPassData, a, want, 1,
                  es * ((double)h->ld[ds] * k + n + (n - k)));
@@ -393,6 +442,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
   // y = (I - V_G T_G V_G') Delta_G w, w = [p[:k]; (nu/nu_G) g[k:]]
   {
     PassArgs a = pass_base(h, gs);
+    a.partials = h->partials2;
     a.k = k;
     a.z = h->zG;
     a.head = h->head;
@@ -401,22 +451,33 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.step = (uint32_t)step;
     a.want_ysq = want_ysq;
     a.dyn = dyn;
-    a.pf = pf ? 1 : 0;
+    a.pf = pl.pf_rand ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    const After want = after_of(ranges(0, pf ? k + 1 : 0, h->extra, kNumExtra),
-                              h->P[gs].red, 0);
-    rc = do_pass(h, gs, kPassRandHaar, a, want, 2,
-                 es * ((double)h->ld[gs] * k + n + (n - k) +
-                       (dyn.kind ? 2.0 * n : 0.0)));
-    if (rc) return rc;
+    const After want =
+        after_of(ranges(0, pl.pf_rand ? k + 1 : 0, h->extra,
+                        (pl.pf_rand || want_ysq) ? kNumExtra : 0),
+                 h->P[gs].red, 0);
+    {
+      ProfScope ps(h, 2,
+                   es * ((double)h->ld[gs] * k + n + (n - k) +
+                         (dyn.kind ? 2.0 * n : 0.0)));
+      LCHK(launch_pass(h->f64, h->sh[gs], kPassRandHaar, a, h->stream));
+    }
+    defer_after(h, gs, want);
+    if (want_ysq) {
+      // ||y||^2 is read right after the query
+      After none = after_of(ranges(0, 0), h->P[gs].red, 0);
+      rc = run_after(h, gs, none);
+      if (rc) return rc;
+    }
   }
   h->t = step;
   h->r = step;
   h->l = step;
-  h->pf_step[ds] = pf ? step + 1 : 0;
-  h->pf_step[gs] = pf ? step + 1 : 0;
-  h->pending[ds] = k;
+  h->pf_step[ds] = pl.pf_data ? step + 1 : 0;
+  h->pf_step[gs] = pl.pf_rand ? step + 1 : 0;
+  h->pending[ds] = pl.tcol ? -1 : k;
   return HD_OK;
 }
 
@@ -444,7 +505,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     rc = prefetch(h, gs, kG, step, kG - 1, 0);
     if (rc) return rc;
   }
-  const bool pf = step + 1 <= h->cfg.t_max;
+  const Plan pl = plan_of(h, ds, step);
   rc = data_tdot(h, ds, x, kD, kG);
   if (rc) return rc;
   {
@@ -454,11 +515,13 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.x = x;
     a.head = h->head;
     a.pivot = h->scal;
-    a.pf = pf ? 1 : 0;
+    a.pf = pl.pf_data ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kD;
-    After want = after_of(ranges(0, pf ? kD + 1 : 0, h->extra, kNumExtra),
-                        h->P[ds].red, 3);
+    a.cslot = pl.tcol && kD > 0 ? h->slot2 : -1;
+    After want = after_of(ranges(0, pl.pf_data ? kD + 1 : 0, h->slot2,
+                                 a.cslot >= 0 ? kD : 0, h->extra, kNumExtra),
+                          h->P[ds].red, 3);
     GinSmallArgs& gsa = want.gs;
     gsa.D = h->P[ds];
     gsa.G = h->P[gs];
@@ -471,6 +534,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     gsa.pivot = h->scal;
     gsa.scal = h->gscal;
     gsa.D_extra = h->extra;
+    gsa.cslot = a.cslot;
     gsa.flag = h->flag;
     rc = do_pass(h, ds, kPassData, a, want, 1,
                  es * ((double)h->ld[ds] * kD + nD + (nD - kD)));
@@ -495,27 +559,30 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.key = Key{h->cfg.seed, h->cfg.trial};
     a.step = (uint32_t)step;
     a.dyn = dyn;
-    a.pf = pf ? 1 : 0;
+    a.pf = pl.pf_rand ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kG - 1;
-    a.partials = h->partials;
+    a.partials = h->partials2;
     a.pstride = h->pstride;
     a.extra = h->extra;
-    const After want = after_of(ranges(0, pf ? kG : 0), h->P[gs].red,
-                              0);
-    rc = do_gin_pass(h, gs, a, want,
-                     es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
-                           (dyn.kind ? 2.0 * nG : 0.0)));
-    if (rc) return rc;
+    const After want = after_of(ranges(0, pl.pf_rand ? kG : 0),
+                                h->P[gs].red, 0);
+    {
+      ProfScope ps(h, 2,
+                   es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
+                         (dyn.kind ? 2.0 * nG : 0.0)));
+      LCHK(launch_gin_pass(h->f64, h->sh[gs], a, h->stream));
+    }
+    defer_after(h, gs, want);
   }
   h->t = step;
   if (ds == 0)
     h->r = kD + 1;
   else
     h->l = kD + 1;
-  h->pending[ds] = kD;
-  h->pf_step[ds] = pf ? step + 1 : 0;
-  h->pf_step[gs] = pf ? step + 1 : 0;
+  h->pending[ds] = pl.tcol ? -1 : kD;
+  h->pf_step[ds] = pl.pf_data ? step + 1 : 0;
+  h->pf_step[gs] = pl.pf_rand ? step + 1 : 0;
   return HD_OK;
 }
 
@@ -612,6 +679,9 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
     h->pending[s] = -1;
   }
   ALLOC(h->partials, sizeof(double) * (size_t)maxwg * h->pstride);
+  ALLOC(h->partials2, sizeof(double) * (size_t)maxwg * h->pstride);
+  h->hint = -1;
+  h->deferred = no_job();
   ALLOC(h->w, sizeof(double) * h->pstride);
   ALLOC(h->zD, sizeof(double) * tm);
   ALLOC(h->zG, sizeof(double) * 3 * (size_t)tm);
@@ -663,6 +733,8 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial) {
     h->pf_step[s] = 0;
     h->pending[s] = -1;
   }
+  h->hint = -1;
+  h->deferred = no_job();
   return HD_OK;
 }
 
@@ -770,6 +842,8 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
     const int transpose = (dyn->pattern == HD_PATTERN_ALT && t % 2 == 0);
     void* y = traj_y ? (char*)traj_y + (size_t)(t - 1) * vb : h->ybuf;
     const void* xprev = t == 1 ? xprev0 : xrow(t - 1);
+    h->hint = t < T ? (dyn->pattern == HD_PATTERN_ALT && (t + 1) % 2 == 0)
+                    : kHintNone;
     DynFuse fz = no_dyn();
     if (dyn->kind == HD_DYN_TANH || dyn->kind == HD_DYN_SOFT_HIST) {
       // element-wise maps run in the random-side pass epilogue
@@ -782,6 +856,7 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
     }
     int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE,
                    fz);
+    h->hint = -1;
     if (rc) return rc;
     if (fz.kind) continue;
     DynArgs d;

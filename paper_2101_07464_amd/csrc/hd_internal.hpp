@@ -70,6 +70,8 @@ struct HaarSmallArgs {
   Key key;
   uint32_t step;
   int extra;
+  int cslot;        // >= 0: complete T_D column k from D.red[cslot..] (the
+                    // data pass's dots of V_D[:, :k] with rows > k of u_k)
   int* flag;
 };
 
@@ -86,6 +88,7 @@ struct GinSmallArgs {
   const double* pivot;
   double* scal;     // out: [0] nu; [1] sigma (set by the host)
   int D_extra;      // offset of the extra slots in D.red
+  int cslot;        // >= 0: complete T_D column k (as in HaarSmallArgs)
   int* flag;
 };
 
@@ -141,6 +144,8 @@ struct PassArgs {
   const void* x;
   double* head;   // rows < k of the output (FP64)
   double* pivot;  // row k of the output (FP64)
+  int cslot;      // >= 0: also the dots of columns 0..k-1 with rows > k of
+                  // the new column (a second sweep), into slots cslot + j
   // random (Haar) mode: y = Delta w - V z, w = [head; cscale * g_step]
   const double* cscale;
   void* y;
@@ -248,8 +253,18 @@ int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                 hipStream_t s);
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s);
-int launch_reduce(const double* partials, int pstride, int nwg,
-                  const SlotRanges& r, double* out, hipStream_t s);
+// Fixed-order sums of the partial rows of one pass: out[slot] = sum over
+// rows w < nwg of P[w * pstride + slot], for the slots in rg.
+struct ReduceJob {
+  const double* P;
+  int pstride;
+  int nwg;
+  SlotRanges rg;
+  double* out;
+};
+
+// One launch for one or two jobs (job b may have no slots).
+int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s);
 int launch_small_data(const SmallDataArgs& a, hipStream_t s);
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);
 int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s);

@@ -164,7 +164,8 @@ __device__ void small_data_body(const SmallDataArgs& a) {
 // the identity (tau = 0, no sign).  Written by one thread; returns nu.
 template <typename T>
 __device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
-                                 double pk, int* flag) {
+                                 double pk, int* flag, double* up_out,
+                                 double* tau_out) {
   T* V = (T*)D.V;
   const double nu = sqrt(ss + pk * pk);
   double s = 1.0, tau = 0.0, up = 0.0;
@@ -181,7 +182,28 @@ __device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
   D.sgn[k] = s;
   D.pi[k + 1] = nu > 0.0 ? D.pi[k] * (-s) : D.pi[k];
   D.T[k + (int64_t)k * tm] = tau;
+  *up_out = up;
+  *tau_out = tau;
   return nu;
+}
+
+// Column k of the data side's T factor from the dots c_j (j < k) of its
+// columns with the stored rows > k of u_k, summed by the data pass: adds the
+// pivot row (V[k, j] * u_k[k]), then T[:k, k] = -tau_k T[:k, :k] c.  c is
+// updated in place.  Two barriers; every thread of the workgroup calls it.
+template <typename T>
+__device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
+                          double tau, double* c) {
+  const T* V = (const T*)D.V;
+  for (int j = threadIdx.x; j < k; j += kWG)
+    c[j] += (double)V[(int64_t)j * D.ld + k] * up;
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += kWG) {
+    double s = 0.0;
+    for (int l = j; l < k; ++l) s += D.T[j + (int64_t)l * tm] * c[l];
+    D.T[j + (int64_t)k * tm] = -tau * s;
+  }
+  __syncthreads();
 }
 
 // Haar, after the data-side pass of query t (k = t-1 reflectors per panel):
@@ -191,7 +213,7 @@ __device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
 // before L_1..L_{t-1}), and z_G = T_G s_vec.
 template <typename T>
 __device__ void haar_small_body(const HaarSmallArgs& a) {
-  __shared__ double sh[4];
+  __shared__ double sh[6];
   const int k = a.k, tid = threadIdx.x, tm = a.tmax;
   T* VG = (T*)a.G.V;
   const int64_t ldG = a.G.ld;
@@ -200,7 +222,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
   if (tid == 0) {
     const double nu = data_reflector<T>(a.D, k, tm,
                                         a.D.red[a.extra + kSlotSS], *a.pivot,
-                                        a.flag);
+                                        a.flag, &sh[4], &sh[5]);
     const PhiloxKey key{a.key.k0, a.key.k1};
     const double gk = normal_at(key, a.step, 0u, (uint64_t)k);
     const double ssG = a.G.red[a.extra + kSlotPFSS];
@@ -248,6 +270,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
     a.zG[j] = zz;
     a.G.T[j + (int64_t)k * tm] = -tauG * tG;
   }
+  if (a.cslot >= 0) data_tcol<T>(a.D, k, tm, sh[4], sh[5], a.D.red + a.cslot);
 }
 
 // Ginibre: the data reflector, then the random-side coefficients
@@ -255,7 +278,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
 // s2 = V_G' Delta_G h (head rows only) + nu s1; z1 = T_G s1, z2 = T_G s2.
 template <typename T>
 __device__ void gin_small_body(const GinSmallArgs& a) {
-  __shared__ double sh[1];
+  __shared__ double sh[3];
   const int k = a.k, l = a.l, tid = threadIdx.x, tm = a.tmax;
   const T* VG = (const T*)a.G.V;
   const int64_t ldG = a.G.ld;
@@ -264,7 +287,7 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   if (tid == 0) {
     const double nu = data_reflector<T>(a.D, k, tm,
                                         a.D.red[a.D_extra + kSlotSS], *a.pivot,
-                                        a.flag);
+                                        a.flag, &sh[1], &sh[2]);
     a.scal[0] = nu;
     sh[0] = nu;
   }
@@ -290,6 +313,7 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
     a.z1[j] = z1;
     a.z2[j] = z2;
   }
+  if (a.cslot >= 0) data_tcol<T>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot);
 }
 
 // Element-wise map f_t on one row (y already rounded to storage).
@@ -381,6 +405,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
 
   // Epilogue: form the output rows, write the new column k, and the extras.
   double ssq = 0.0, pfnew = 0.0, ysq = 0.0;
+  double ur[CPT][RPL];  // stored rows > k of the new column (data mode)
   const double pik = a.pi[k];
   const double cs = (MODE == kPassRandHaar) ? *a.cscale : 0.0;
 #pragma unroll
@@ -393,6 +418,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
 #pragma unroll
     for (int e = 0; e < RPL; ++e) {
       const int64_t i = i0 + e;
+      ur[c][e] = 0.0;
       if (i >= a.n) continue;
       const double sg = (i < k) ? a.pi[i + 1] : pik;
       if (MODE == kPassData) {
@@ -405,6 +431,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
           const T ps = (T)p;
           V[(int64_t)k * a.ld + i] = ps;
           const double pd = (double)ps;
+          ur[c][e] = pd;
           ssq += pd * pd;
           pfnew += pd * gn[c][e];
         }
@@ -427,6 +454,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
         }
       }
     }
+  }
+  if (MODE == kPassData && a.cslot >= 0) {
+    // dots of the earlier columns with the new one, for its T column (these
+    // rows of V were just read, so they mostly come from L2)
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+      if (!cvalid[c]) {
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) ur[c][e] = 0.0;
+      }
+    sweep<T, RPL, CPT, 1, 0>(V, a.ld, k, blk0, cvalid, ur, ur, true, nullptr,
+                             0.0, nullptr, 0.0, acc, acc, wacc, out + a.cslot,
+                             nullptr);
   }
   if (MODE == kPassData) {
     const double s = block_sum(ssq, scr);
@@ -600,12 +640,8 @@ __global__ __launch_bounds__(kWG) void k_trial_small(int op,
 
 // ------------------------------------------------- standalone kernels ----
 
-__global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ P,
-                                                int pstride, int nwg,
-                                                SlotRanges rg,
-                                                double* __restrict__ out) {
-  __shared__ double scr[kWaves];
-  int b = blockIdx.x, slot = -1;
+__device__ __forceinline__ int slot_of(const SlotRanges& rg, int b) {
+  int slot = -1;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     if (slot < 0) {
@@ -615,11 +651,20 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ P,
         b -= rg.count[q];
     }
   }
+  return slot;
+}
+
+__global__ __launch_bounds__(kWG) void k_reduce(ReduceJob ja, ReduceJob jb) {
+  __shared__ double scr[kWaves];
+  const int na = ja.rg.count[0] + ja.rg.count[1] + ja.rg.count[2];
+  const bool first = (int)blockIdx.x < na;
+  const ReduceJob& j = first ? ja : jb;
+  const int slot = slot_of(j.rg, first ? blockIdx.x : blockIdx.x - na);
   double s = 0.0;
-  for (int w = threadIdx.x; w < nwg; w += kWG)
-    s += P[(int64_t)w * pstride + slot];
+  for (int w = threadIdx.x; w < j.nwg; w += kWG)
+    s += j.P[(int64_t)w * j.pstride + slot];
   s = block_sum(s, scr);
-  if (threadIdx.x == 0) out[slot] = s;
+  if (threadIdx.x == 0) j.out[slot] = s;
 }
 
 __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
@@ -808,12 +853,11 @@ int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
   return 0;
 }
 
-int launch_reduce(const double* partials, int pstride, int nwg,
-                  const SlotRanges& r, double* out, hipStream_t s) {
-  const int total = r.count[0] + r.count[1] + r.count[2];
-  if (total <= 0) return 0;
-  hipLaunchKernelGGL(k_reduce, dim3(total), dim3(kWG), 0, s, partials,
-                     pstride, nwg, r, out);
+int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s) {
+  const int na = a.rg.count[0] + a.rg.count[1] + a.rg.count[2];
+  const int nb = b.rg.count[0] + b.rg.count[1] + b.rg.count[2];
+  if (na + nb <= 0) return 0;
+  hipLaunchKernelGGL(k_reduce, dim3(na + nb), dim3(kWG), 0, s, a, b);
   HD_CHECK_LAUNCH();
   return 0;
 }
