@@ -95,20 +95,16 @@ int env_int(const char* name, int dflt) {
 }
 
 
-// Panels up to 256K rows use one row per lane (256-row workgroups, so even
-// n = 65536 fills the chip); larger ones four rows per lane in chunks of
-// 1024 rows, cpt chunks per workgroup.  HD_RPL / HD_CPT override (tuning).
+// Workgroups cover 256 * cpt rows: one chunk up to 512K rows (at least 256
+// workgroups from n = 65536 on, one per compute unit), two up to 2M, four
+// beyond.  HD_CPT overrides (tuning).
 Shape pick_shape(int64_t dim, int64_t ld) {
   Shape sh;
-  sh.rpl = dim <= ((int64_t)1 << 18) ? 1 : 4;
-  sh.cpt = sh.rpl == 1 ? 1 : (dim >= ((int64_t)1 << 20) ? 4 : 2);
-  const int rpl = env_int("HD_RPL", 0), cpt = env_int("HD_CPT", 0);
-  if (rpl == 1 || rpl == 4) sh.rpl = rpl;
-  if (sh.rpl == 1) sh.cpt = 1;
-  if (sh.rpl == 4 && (cpt == 1 || cpt == 2 || cpt == 4 || cpt == 8))
-    sh.cpt = cpt;
-  const int64_t rows = (int64_t)kWG * sh.rpl * sh.cpt;
-  sh.nwg = (int)((ld + rows - 1) / rows);
+  sh.cpt = dim <= ((int64_t)1 << 19) ? 1 : (dim <= ((int64_t)1 << 21) ? 2 : 4);
+  const int cpt = env_int("HD_CPT", 0);
+  if (cpt == 1 || cpt == 2 || cpt == 4) sh.cpt = cpt;
+  const int64_t rows = (int64_t)256 * sh.cpt;
+  sh.nwg = (int)(ld / rows);
   return sh;
 }
 

@@ -6,7 +6,8 @@
 //  * 64-lane wavefront reductions, including a reduce-scatter that sums CG
 //    per-lane partials over the wave with CG - 1 + log2(64/CG) exchanges
 //    instead of CG full reductions, on permlane swaps and DPP moves (no LDS);
-//  * panel row loads (one 16-byte load per column for four FP32 rows).
+//  * panel row loads (four consecutive rows: one 16-byte load for FP32, two
+//    for FP64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -205,37 +206,6 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[CG]) {
   return rs_tail<32 / CG>(v[0]);
 }
 
-// out[slot] = sum_{w0 <= w < w1} P[w * pstride + slot] in increasing w, one
-// thread per slot; loads are issued eight rows at a time.  Ends with a
-// barrier.
-__device__ __forceinline__ void reduce_rows(const double* P, int pstride,
-                                            int w0, int w1, SlotRanges rg,
-                                            double* out) {
-  const int total = rg.count[0] + rg.count[1] + rg.count[2];
-  for (int s = threadIdx.x; s < total; s += kWG) {
-    int slot;
-    if (s < rg.count[0])
-      slot = rg.start[0] + s;
-    else if (s - rg.count[0] < rg.count[1])
-      slot = rg.start[1] + (s - rg.count[0]);
-    else
-      slot = rg.start[2] + (s - rg.count[0] - rg.count[1]);
-    const double* col = P + slot;
-    double acc = 0.0;
-    int w = w0;
-    for (; w + 8 <= w1; w += 8) {
-      double v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = col[(int64_t)(w + q) * pstride];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc += v[q];
-    }
-    for (; w < w1; ++w) acc += col[(int64_t)w * pstride];
-    out[slot] = acc;
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------- loads ---
 
 __device__ __forceinline__ void load4(const float* __restrict__ p,
@@ -255,19 +225,6 @@ __device__ __forceinline__ void load4(const double* __restrict__ p,
   out[1] = a.y;
   out[2] = b.x;
   out[3] = b.y;
-}
-
-// RPL consecutive panel entries of one lane (RPL = 4: one 16-byte load for
-// FP32, two for FP64; RPL = 1: one element).
-template <int RPL, typename T>
-__device__ __forceinline__ void load_rows(const T* __restrict__ p,
-                                          double (&out)[RPL]) {
-  if constexpr (RPL == 4) {
-    load4(p, out);
-  } else {
-#pragma unroll
-    for (int e = 0; e < RPL; ++e) out[e] = (double)p[e];
-  }
 }
 
 }  // namespace hd

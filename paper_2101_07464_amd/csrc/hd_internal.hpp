@@ -205,51 +205,15 @@ struct DynArgs {
   const double* ysq;  // normalise: ||y||^2
 };
 
-// Launch shape of a panel pass: rows per lane (1 or 4), chunks of 256 * rpl
-// rows per workgroup, and the number of workgroups.
+// Launch shape of a panel pass: chunks of 256 rows per workgroup (1, 2 or
+// 4) and the number of workgroups.  The panel's leading dimension is a
+// multiple of 256 * cpt.
 struct Shape {
-  int rpl;
   int cpt;
   int nwg;
 };
 
-// Batched launches: many independent trials at the same query index share
-// one grid.  Block b works for trial blk_trial[b] as its block
-// b - blk_first[trial]; the per-trial arguments live in device memory and the
-// per-step fields (the same for every trial) come from StepPatch.
-struct StepPatch {
-  int k;            // reflectors per panel before this query
-  int kp;           // pending data column of the data side (or -1)
-  uint32_t step;    // 1-based query index
-  int pf;           // prefetch for step + 1
-  int want_ss;
-};
-
-struct BatchMap {
-  const int* blk_trial;
-  const int* blk_first;
-  int nblk;
-};
-
-// Per-trial epilogue of a batched pass, one workgroup per trial: the
-// fixed-order sums of the trial's partial rows, then an optional small step.
-enum TrialOp { kTrialReduce = 0, kTrialSmallData = 1, kTrialHaarSmall = 2 };
-
-struct TrialSums {
-  double* partials;
-  int pstride;
-  int nwg;
-  double* out;
-};
-
 int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s);
-int launch_tdot_batch(int f64, Shape sh, const TdotArgs* args, BatchMap bm,
-                      StepPatch p, int gen, hipStream_t s);
-int launch_pass_batch(int f64, Shape sh, int mode, const PassArgs* args,
-                      BatchMap bm, StepPatch p, hipStream_t s);
-int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
-                       SlotRanges rg, const SmallDataArgs* sd,
-                       const HaarSmallArgs* hs, StepPatch p, hipStream_t s);
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                 hipStream_t s);
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s);

@@ -9,19 +9,23 @@
 // (the -sign(v1) factor of eq. (Householder) commutes with every later
 // reflector, so all of them collect into Delta).
 //
-// Every panel kernel is one streaming sweep over its rows (RPL rows per lane:
-// 4 = one 16-byte load per column for FP32, 1 for small panels to give them
-// more workgroups) with all accumulation in FP64:
+// Every panel kernel is one streaming sweep over its rows, with all
+// accumulation in FP64.  A lane holds four consecutive rows (one 16-byte load
+// per FP32 column, two per FP64 column), a chunk is the 256 rows of one
+// wave's 64 lanes, and a workgroup covers CPT chunks; its four waves split
+// the columns (wave w takes columns w, w + 4, w + 8, ...), so every wave has
+// a full chunk of rows in flight per column even when the panel is short.
 //   tdot     : w = V' b (column dots), optionally a second right-hand side
-//   pass     : out = Delta a - V z (GEMV-N), the new panel column, and the dots
-//              of every column with the next query's Philox draw (prefetch)
+//   pass     : out = Delta a - V z (GEMV-N), the new panel column, the dots of
+//              every column with the next query's Philox draw (prefetch) and,
+//              when asked, of the earlier columns with the new one
 //   gin_pass : the random side of a Ginibre query (two GEMV-N plus the
 //              explicit basis panel)
-// Column dots are summed per wave with a barrier-free reduce-scatter into an
-// LDS window, per workgroup in fixed order, and across workgroups by k_reduce
-// (or k_trial_small for batches) in fixed order, so results are bitwise
-// reproducible run to run.  Small one-workgroup FP64 kernels update the WY
-// factor T and the reflector scalars.
+// Column dots are summed per wave with a reduce-scatter on permlane swaps
+// and DPP moves, across workgroups by k_reduce in fixed order, so results
+// are bitwise reproducible run to run.  GEMV-N rows are summed over the four
+// waves through LDS in fixed order.  Small one-workgroup FP64 kernels update
+// the WY factor T and the reflector scalars.
 #include <hip/hip_runtime.h>
 
 #include "hd_device.hpp"
@@ -29,132 +33,225 @@
 
 namespace hd {
 
-constexpr int kFlush = 256;  // columns per LDS window of the column sums
+constexpr int kLaneRows = 4;                  // consecutive rows per lane
+constexpr int kChunkRows = 64 * kLaneRows;    // rows of one wave (256)
+// Columns per group of a wave's sweep.  Each lane keeps one partial sum per
+// column of the group in registers and the compiler issues all CG * CPT
+// loads of a group together, so groups narrow as chunks are added (wider
+// groups spill to scratch).
+template <int CPT, int ND, int NZ>
+constexpr int col_group() {
+  return (ND <= 1 && NZ == 0) ? 16 : 8 / CPT;
+}
 
-// Columns per group of the panel sweeps: each lane keeps one partial sum per
-// column of the group in registers (wider groups spill to scratch).
-constexpr int kCG = 16;
-
-// Draws g_step[i] for the RPL rows i0..i0+RPL-1 of one lane; rows outside
+// Draws g_step[i] for the four rows i0..i0+3 of one lane; rows outside
 // (lo, n) get 0.  Values are rounded to the storage type when `round`.
-template <typename T, int RPL>
+template <typename T>
 __device__ __forceinline__ void draw_rows(PhiloxKey key, uint32_t step,
                                           int64_t i0, int64_t lo, int64_t n,
-                                          bool round, double (&out)[RPL]) {
+                                          bool round, double (&out)[4]) {
 #pragma unroll
-  for (int e = 0; e < RPL; ++e) out[e] = 0.0;
-  if (i0 >= n || i0 + RPL - 1 <= lo) return;
+  for (int e = 0; e < 4; ++e) out[e] = 0.0;
+  if (i0 >= n || i0 + 3 <= lo) return;
   double g[4];
   normals4(key, step, 0u, (uint64_t)(i0 >> 2), g);
 #pragma unroll
-  for (int e = 0; e < RPL; ++e) {
+  for (int e = 0; e < 4; ++e) {
     const int64_t i = i0 + e;
-    const double v = g[(RPL == 4) ? e : (int)(i & 3)];
-    if (i > lo && i < n) out[e] = round ? (double)(T)v : v;
+    if (i > lo && i < n) out[e] = round ? (double)(T)g[e] : g[e];
   }
 }
 
-// One sweep over columns [0, nc) of a panel, over the rows of this workgroup
-// (CPT chunks of kWG * RPL rows starting at blk0):
-//   dots (ND = 1 or 2, when `dots`): d0[j] = sum_rows V[r, j] * rhs0[r]
-//        -> out0[j], and likewise rhs1 -> out1 (per-workgroup partials);
-//   GEMV-N (NZ = 0, 1 or 2): acc_q[r] -= zs_q * sum_j V[r, j] * z_q[j].
-template <typename T, int RPL, int CPT, int ND, int NZ>
+// The draw of `step` for the CPT * 256 rows of a workgroup into LDS
+// (g[q] for row blk0 + q), computed once per workgroup: one Philox block of
+// four normals per thread.  The caller synchronises before reading.
+template <typename T, int CPT>
+__device__ __forceinline__ void draw_block(PhiloxKey key, uint32_t step,
+                                           int64_t blk0, int64_t lo, int64_t n,
+                                           bool round, double* g) {
+  for (int q = threadIdx.x; q < CPT * 64; q += kWG) {
+    double v[4];
+    draw_rows<T>(key, step, blk0 + 4 * (int64_t)q, lo, n, round, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) g[4 * q + e] = v[e];
+  }
+}
+
+// The lane's four rows of chunk c from a workgroup vector in LDS.
+template <int CPT>
+__device__ __forceinline__ void lane_rows(const double* g,
+                                          double (&out)[CPT][4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[c][e] = g[c * kChunkRows + 4 * lane + e];
+}
+
+// Sum over the four waves (fixed order) of the lane-layout partial rows acc:
+// afterwards thread t holds in out[c] the total for row c * 256 + t of the
+// workgroup.  `lds` holds kWaves * CPT * 256 doubles.  Two barriers.
+template <int CPT>
+__device__ __forceinline__ void combine_rows(const double (&acc)[CPT][4],
+                                             double* lds, double (&out)[CPT]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      lds[(wave * CPT + c) * kChunkRows + 4 * lane + e] = acc[c][e];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += lds[(w * CPT + c) * kChunkRows + tid];
+    out[c] = s;
+  }
+  __syncthreads();
+}
+
+// One sweep of this wave's columns (j = wave + 4 q < nc) of a panel over the
+// workgroup's rows (CPT chunks from blk0):
+//   dots (ND = 1 or 2, when `dots`): sum_rows V[r, j] * rhs0[r] -> out0[j],
+//        and likewise rhs1 -> out1 (per-workgroup partials);
+//   GEMV-N (NZ = 0, 1 or 2): acc_q[r] -= zs_q * sum_j V[r, j] * z_q[j] over
+//        this wave's columns (rows are summed over waves afterwards).
+// Every panel row of the workgroup is allocated (ld is a multiple of the
+// workgroup's rows); rows at or beyond n are zero.
+template <typename T, int CPT, int ND, int NZ>
 __device__ __forceinline__ void sweep(
     const T* __restrict__ V, int64_t ld, int nc, int64_t blk0,
-    const bool (&cvalid)[CPT], const double (&rhs0)[CPT][RPL],
-    const double (&rhs1)[CPT][RPL], bool dots, const double* __restrict__ z0,
-    double zs0, const double* __restrict__ z1, double zs1,
-    double (&acc0)[CPT][RPL], double (&acc1)[CPT][RPL], double* wacc,
-    double* out0, double* out1) {
-  constexpr int CG = kCG;
-  constexpr int kRows = kWG * RPL;
-  constexpr int kGroup = 64 / CG;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double (&rhs0)[CPT][4], const double (&rhs1)[CPT][4], bool dots,
+    const double* __restrict__ z0, double zs0, const double* __restrict__ z1,
+    double zs1, double (&acc0)[CPT][4], double (&acc1)[CPT][4], double* out0,
+    double* out1) {
+  constexpr int kCG = col_group<CPT, ND, NZ>();
+  constexpr int kGroup = 64 / kCG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ncw = nc > wave ? (nc - wave + kWaves - 1) / kWaves : 0;
+  const T* __restrict__ Vl = V + blk0 + 4 * lane;
 #pragma unroll 1
-  for (int w0 = 0; w0 < nc; w0 += kFlush) {
-    const int wend = min(nc, w0 + kFlush);
-#pragma unroll 1
-    for (int j0 = w0; j0 < wend; j0 += CG) {
-      double p0[CG], p1[ND == 2 ? CG : 1];
-      double q0[NZ >= 1 ? CG : 1], q1[NZ == 2 ? CG : 1];
+  for (int g0 = 0; g0 < ncw; g0 += kCG) {
+    double p0[kCG], p1[ND == 2 ? kCG : 1];
+    double q0[NZ >= 1 ? kCG : 1], q1[NZ == 2 ? kCG : 1];
 #pragma unroll
-      for (int jj = 0; jj < CG; ++jj) {
-        const bool ok = j0 + jj < nc;
-        p0[jj] = 0.0;
-        if constexpr (ND == 2) p1[jj] = 0.0;
-        if constexpr (NZ >= 1) q0[jj] = ok ? zs0 * z0[j0 + jj] : 0.0;
-        if constexpr (NZ == 2) q1[jj] = ok ? zs1 * z1[j0 + jj] : 0.0;
-      }
+    for (int jj = 0; jj < kCG; ++jj) {
+      const bool ok = g0 + jj < ncw;
+      const int j = wave + kWaves * (g0 + jj);
+      p0[jj] = 0.0;
+      if constexpr (ND == 2) p1[jj] = 0.0;
+      if constexpr (NZ >= 1) q0[jj] = ok ? zs0 * z0[j] : 0.0;
+      if constexpr (NZ == 2) q1[jj] = ok ? zs1 * z1[j] : 0.0;
+    }
 #pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        if (!cvalid[c]) continue;
-        const int64_t r = blk0 + (int64_t)c * kRows + RPL * tid;
+    for (int c = 0; c < CPT; ++c) {
 #pragma unroll
-        for (int jj = 0; jj < CG; ++jj) {
-          const int j = min(j0 + jj, nc - 1);
-          double v[RPL];
-          load_rows<RPL>(V + (int64_t)j * ld + r, v);
+      for (int jj = 0; jj < kCG; ++jj) {
+        const int j = wave + kWaves * min(g0 + jj, ncw - 1);
+        double v[4];
+        load4(Vl + (int64_t)j * ld + c * kChunkRows, v);
 #pragma unroll
-          for (int e = 0; e < RPL; ++e) {
-            if constexpr (NZ >= 1) acc0[c][e] -= v[e] * q0[jj];
-            if constexpr (NZ == 2) acc1[c][e] -= v[e] * q1[jj];
-            if constexpr (ND >= 1) p0[jj] += v[e] * rhs0[c][e];
-            if constexpr (ND == 2) p1[jj] += v[e] * rhs1[c][e];
-          }
-        }
-      }
-      if constexpr (ND >= 1) {
-        if (dots) {
-          const int col = j0 + lane / kGroup;
-          const bool owner = (lane % kGroup) == 0 && col < wend;
-          const double s0 = wave_reduce_scatter<CG>(p0);
-          if (owner) wacc[wave * kFlush + (col - w0)] = s0;
-          if constexpr (ND == 2) {
-            const double s1 = wave_reduce_scatter<CG>(p1);
-            if (owner) wacc[(kWaves + wave) * kFlush + (col - w0)] = s1;
-          }
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (NZ >= 1) acc0[c][e] -= v[e] * q0[jj];
+          if constexpr (NZ == 2) acc1[c][e] -= v[e] * q1[jj];
+          if constexpr (ND >= 1) p0[jj] += v[e] * rhs0[c][e];
+          if constexpr (ND == 2) p1[jj] += v[e] * rhs1[c][e];
         }
       }
     }
-    if (ND >= 1 && dots) {
-      __syncthreads();
-      for (int jj = tid; jj < wend - w0; jj += kWG) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-          s0 += wacc[w * kFlush + jj];
-          if (ND == 2) s1 += wacc[(kWaves + w) * kFlush + jj];
+    if constexpr (ND >= 1) {
+      if (dots) {
+        const int q = g0 + lane / kGroup;
+        const bool owner = (lane % kGroup) == 0 && q < ncw;
+        const double s0 = wave_reduce_scatter<kCG>(p0);
+        if (owner) out0[wave + kWaves * q] = s0;
+        if constexpr (ND == 2) {
+          const double s1 = wave_reduce_scatter<kCG>(p1);
+          if (owner) out1[wave + kWaves * q] = s1;
         }
-        out0[w0 + jj] = s0;
-        if (ND == 2) out1[w0 + jj] = s1;
       }
-      __syncthreads();
     }
   }
 }
 
 // ------------------------------------------------- small FP64 steps ------
+//
+// The small steps are O(k^2) sums over the T factors and the head rows of the
+// panels.  One thread per output with a serial loop would issue its loads one
+// small batch at a time; instead P = 256 / nout threads share each output,
+// each summing a strided subset of the terms (so every thread has only a few
+// independent loads, all issued at once), and the P partial sums are added
+// through LDS in fixed order.
+
+// out(j, s_j) for j < nout with s_j = sum over i in [lo(j), hi(j)) of
+// term(i, j); with two terms (NT = 2) both sums share the loop.  Every thread
+// of the workgroup calls it; `lds` holds 2 * kWG doubles.  Ends with a
+// barrier.
+template <int NT, typename Lo, typename Hi, typename Term, typename Out>
+__device__ __forceinline__ void wg_sums(int nout, Lo lo, Hi hi, Term term,
+                                        Out out, double* lds) {
+  if (nout <= 0) return;
+  const int tid = threadIdx.x;
+  const int P = nout >= kWG ? 1 : kWG / nout;  // threads per output
+  const int per = kWG / P;                     // outputs per round
+  for (int base = 0; base < nout; base += per) {
+    const int j = base + tid / P, ph = tid % P;
+    double s0 = 0.0, s1 = 0.0;
+    if (tid / P < per && j < nout) {
+      const int h = hi(j);
+#pragma unroll 8
+      for (int i = lo(j) + ph; i < h; i += P) {
+        double t0, t1;
+        term(i, j, t0, t1);
+        s0 += t0;
+        if (NT == 2) s1 += t1;
+      }
+    }
+    lds[tid] = s0;
+    if (NT == 2) lds[kWG + tid] = s1;
+    __syncthreads();
+    if (ph == 0 && tid / P < per && j < nout) {
+      double r0 = 0.0, r1 = 0.0;
+      for (int q = 0; q < P; ++q) {
+        r0 += lds[tid + q];
+        if (NT == 2) r1 += lds[kWG + tid + q];
+      }
+      out(j, r0, r1);
+    }
+    __syncthreads();
+  }
+}
 
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
 // Schreiber and Van Loan), then z = T' w for the leading k x k block.
 __device__ void small_data_body(const SmallDataArgs& a) {
+  __shared__ double lds[2 * kWG];
   const int tm = a.tmax, kp = a.kp;
+  const double* __restrict__ Tm = a.T;
   if (kp > 0) {
     const double tau = a.tau[kp];
-    for (int j = threadIdx.x; j < kp; j += kWG) {
-      double s = 0.0;
-      for (int l = j; l < kp; ++l) s += a.T[j + (int64_t)l * tm] * a.c[l];
-      a.T[j + (int64_t)kp * tm] = -tau * s;
-    }
+    const double* c = a.c;
+    double* Tw = a.T;
+    wg_sums<1>(
+        kp, [](int j) { return j; }, [kp](int) { return kp; },
+        [=](int l, int j, double& t0, double& t1) {
+          t0 = Tm[j + (int64_t)l * tm] * c[l];
+          t1 = 0.0;
+        },
+        [=](int j, double r0, double) { Tw[j + (int64_t)kp * tm] = -tau * r0; },
+        lds);
   }
-  __syncthreads();
   if (a.w) {
-    for (int j = threadIdx.x; j < a.k; j += kWG) {
-      double s = 0.0;
-      for (int i = 0; i <= j; ++i) s += a.T[i + (int64_t)j * tm] * a.w[i];
-      a.z[j] = s;
-    }
+    const double* w = a.w;
+    double* z = a.z;
+    wg_sums<1>(
+        a.k, [](int) { return 0; }, [](int j) { return j + 1; },
+        [=](int i, int j, double& t0, double& t1) {
+          t0 = Tm[i + (int64_t)j * tm] * w[i];
+          t1 = 0.0;
+        },
+        [=](int j, double r0, double) { z[j] = r0; }, lds);
   }
 }
 
@@ -188,22 +285,25 @@ __device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
 }
 
 // Column k of the data side's T factor from the dots c_j (j < k) of its
-// columns with the stored rows > k of u_k, summed by the data pass: adds the
-// pivot row (V[k, j] * u_k[k]), then T[:k, k] = -tau_k T[:k, :k] c.  c is
-// updated in place.  Two barriers; every thread of the workgroup calls it.
+// columns with the stored rows > k of u_k, summed by the data pass, plus the
+// pivot row (V[k, j] * u_k[k]): T[:k, k] = -tau_k T[:k, :k] c.  Every thread
+// of the workgroup calls it.
 template <typename T>
 __device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
-                          double tau, double* c) {
-  const T* V = (const T*)D.V;
-  for (int j = threadIdx.x; j < k; j += kWG)
-    c[j] += (double)V[(int64_t)j * D.ld + k] * up;
-  __syncthreads();
-  for (int j = threadIdx.x; j < k; j += kWG) {
-    double s = 0.0;
-    for (int l = j; l < k; ++l) s += D.T[j + (int64_t)l * tm] * c[l];
-    D.T[j + (int64_t)k * tm] = -tau * s;
-  }
-  __syncthreads();
+                          double tau, const double* c, double* lds) {
+  const T* __restrict__ V = (const T*)D.V;
+  const double* __restrict__ Tm = D.T;
+  double* Tw = D.T;
+  const int64_t ld = D.ld;
+  wg_sums<1>(
+      k, [](int j) { return j; }, [k](int) { return k; },
+      [=](int l, int j, double& t0, double& t1) {
+        t0 = Tm[j + (int64_t)l * tm] *
+             (c[l] + (double)V[(int64_t)l * ld + k] * up);
+        t1 = 0.0;
+      },
+      [=](int j, double r0, double) { Tw[j + (int64_t)k * tm] = -tau * r0; },
+      lds);
 }
 
 // Haar, after the data-side pass of query t (k = t-1 reflectors per panel):
@@ -214,6 +314,7 @@ __device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
 template <typename T>
 __device__ void haar_small_body(const HaarSmallArgs& a) {
   __shared__ double sh[6];
+  __shared__ double lds[2 * kWG];
   const int k = a.k, tid = threadIdx.x, tm = a.tmax;
   T* VG = (T*)a.G.V;
   const int64_t ldG = a.G.ld;
@@ -250,27 +351,41 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
   __syncthreads();
   const double tauG = sh[0], cs = sh[1], gk = sh[2], upG = sh[3];
   const double piGk = a.G.pi[k];
-  for (int j = tid; j < k; j += kWG) {
-    const T* colG = VG + (int64_t)j * ldG;
-    double hg = 0.0;
-    for (int i = 0; i < k; ++i)
-      hg += (double)colG[i] * a.G.pi[i + 1] * a.head[i];
-    const double gdot = a.G.red[j];
-    cG[j] = gdot + (double)colG[k] * upG;
-    sv[j] = hg + piGk * cs * (gdot + (double)colG[k] * gk);
-  }
-  __syncthreads();
-  for (int j = tid; j < k; j += kWG) {
-    double tG = 0.0, zz = 0.0;
-    for (int l = j; l < k; ++l) {
-      const double tjl = a.G.T[j + (int64_t)l * tm];
-      tG += tjl * cG[l];
-      zz += tjl * sv[l];
-    }
-    a.zG[j] = zz;
-    a.G.T[j + (int64_t)k * tm] = -tauG * tG;
-  }
-  if (a.cslot >= 0) data_tcol<T>(a.D, k, tm, sh[4], sh[5], a.D.red + a.cslot);
+  const T* __restrict__ VGr = VG;
+  const double* __restrict__ piG = a.G.pi;
+  const double* __restrict__ head = a.head;
+  const double* __restrict__ gdot = a.G.red;
+  // hg_j = sum_{j <= i < k} V_G[i, j] pi_{i+1} head_i; then the dots of the
+  // new random reflector (cG) and s_vec (sv)
+  wg_sums<1>(
+      k, [](int j) { return j; }, [k](int) { return k; },
+      [=](int i, int j, double& t0, double& t1) {
+        t0 = (double)VGr[(int64_t)j * ldG + i] * piG[i + 1] * head[i];
+        t1 = 0.0;
+      },
+      [=](int j, double hg, double) {
+        const double vk = (double)VGr[(int64_t)j * ldG + k];
+        cG[j] = gdot[j] + vk * upG;
+        sv[j] = hg + piGk * cs * (gdot[j] + vk * gk);
+      },
+      lds);
+  const double* __restrict__ TG = a.G.T;
+  double* TGw = a.G.T;
+  double* zG = a.zG;
+  wg_sums<2>(
+      k, [](int j) { return j; }, [k](int) { return k; },
+      [=](int l, int j, double& t0, double& t1) {
+        const double tjl = TG[j + (int64_t)l * tm];
+        t0 = tjl * sv[l];
+        t1 = tjl * cG[l];
+      },
+      [=](int j, double zz, double tg) {
+        zG[j] = zz;
+        TGw[j + (int64_t)k * tm] = -tauG * tg;
+      },
+      lds);
+  if (a.cslot >= 0)
+    data_tcol<T>(a.D, k, tm, sh[4], sh[5], a.D.red + a.cslot, lds);
 }
 
 // Ginibre: the data reflector, then the random-side coefficients
@@ -279,8 +394,9 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
 template <typename T>
 __device__ void gin_small_body(const GinSmallArgs& a) {
   __shared__ double sh[3];
+  __shared__ double lds[2 * kWG];
   const int k = a.k, l = a.l, tid = threadIdx.x, tm = a.tmax;
-  const T* VG = (const T*)a.G.V;
+  const T* __restrict__ VG = (const T*)a.G.V;
   const int64_t ldG = a.G.ld;
   double* s1 = a.z1 + tm;
   double* s2 = a.z1 + 2 * tm;
@@ -294,26 +410,38 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   __syncthreads();
   const double nu = sh[0];
   const double pil = a.G.pi[l];
-  for (int j = tid; j < l; j += kWG) {
-    const T* col = VG + (int64_t)j * ldG;
-    double hs = 0.0;
-    for (int i = 0; i < l; ++i) hs += (double)col[i] * a.G.pi[i + 1] * a.h[i];
-    const double v1 = pil * a.G.red[j];
-    s1[j] = v1;
-    s2[j] = hs + nu * v1;
-  }
-  __syncthreads();
-  for (int j = tid; j < l; j += kWG) {
-    double z1 = 0.0, z2 = 0.0;
-    for (int q = j; q < l; ++q) {
-      const double tjq = a.G.T[j + (int64_t)q * tm];
-      z1 += tjq * s1[q];
-      z2 += tjq * s2[q];
-    }
-    a.z1[j] = z1;
-    a.z2[j] = z2;
-  }
-  if (a.cslot >= 0) data_tcol<T>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot);
+  const double* __restrict__ piG = a.G.pi;
+  const double* __restrict__ h = a.h;
+  const double* __restrict__ gdot = a.G.red;
+  wg_sums<1>(
+      l, [](int j) { return j; }, [l](int) { return l; },
+      [=](int i, int j, double& t0, double& t1) {
+        t0 = (double)VG[(int64_t)j * ldG + i] * piG[i + 1] * h[i];
+        t1 = 0.0;
+      },
+      [=](int j, double hs, double) {
+        const double v1 = pil * gdot[j];
+        s1[j] = v1;
+        s2[j] = hs + nu * v1;
+      },
+      lds);
+  const double* __restrict__ TG = a.G.T;
+  double* z1 = a.z1;
+  double* z2 = a.z2;
+  wg_sums<2>(
+      l, [](int j) { return j; }, [l](int) { return l; },
+      [=](int q, int j, double& t0, double& t1) {
+        const double tjq = TG[j + (int64_t)q * tm];
+        t0 = tjq * s1[q];
+        t1 = tjq * s2[q];
+      },
+      [=](int j, double r0, double r1) {
+        z1[j] = r0;
+        z2[j] = r1;
+      },
+      lds);
+  if (a.cslot >= 0)
+    data_tcol<T>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot, lds);
 }
 
 // Element-wise map f_t on one row (y already rounded to storage).
@@ -326,46 +454,52 @@ __device__ __forceinline__ double dyn_row(const DynFuse& d, double yi,
 
 // ------------------------------------------------------------------ TDOT --
 
-template <typename T, int RPL, int CPT, bool GEN, bool TWO>
+template <typename T, int CPT, bool GEN, bool TWO>
 __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
-  constexpr int kRows = kWG * RPL;
-  __shared__ double wacc[2 * kWaves * kFlush];
+  __shared__ double g[GEN ? CPT * kChunkRows : 1];
   __shared__ double scr[kWaves];
-  const int tid = threadIdx.x;
-  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
-  double rhs[2][CPT][RPL];
-  bool cvalid[CPT];
-  double ss = 0.0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t blk0 = (int64_t)blk * (kChunkRows * CPT);
   const PhiloxKey key{a.key.k0, a.key.k1};
+  double rhs0[CPT][4], rhs1[CPT][4];
+  if (GEN) {
+    draw_block<T, CPT>(key, a.gen_step, blk0, a.lo, a.n, true, g);
+    __syncthreads();
+    lane_rows<CPT>(g, rhs0);
+  }
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kRows;
-    cvalid[c] = row0 < a.ld;
-    const int64_t i0 = row0 + RPL * tid;
-    if (GEN)
-      draw_rows<T, RPL>(key, a.gen_step, i0, a.lo, cvalid[c] ? a.n : 0, true,
-                        rhs[0][c]);
+    const int64_t i0 = blk0 + c * kChunkRows + 4 * lane;
 #pragma unroll
-    for (int e = 0; e < RPL; ++e) {
+    for (int e = 0; e < 4; ++e) {
       const int64_t i = i0 + e;
-      const bool in = cvalid[c] && i < a.n;
       if (!GEN)
-        rhs[0][c][e] = (in && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
-      rhs[1][c][e] = (TWO && in) ? (double)((const T*)a.b2)[i] : 0.0;
-      ss += rhs[0][c][e] * rhs[0][c][e];
+        rhs0[c][e] = (i < a.n && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
+      rhs1[c][e] = (TWO && i < a.n) ? (double)((const T*)a.b2)[i] : 0.0;
     }
   }
   double* out = a.partials + (int64_t)blk * a.pstride;
-  double acc[CPT][RPL];
-  sweep<T, RPL, CPT, TWO ? 2 : 1, 0>((const T*)a.V, a.ld, a.ncols, blk0,
-                                     cvalid, rhs[0], rhs[1], true, nullptr,
-                                     0.0, nullptr, 0.0, acc, acc, wacc, out,
-                                     out + a.slot2);
+  double acc[CPT][4];
+  sweep<T, CPT, TWO ? 2 : 1, 0>((const T*)a.V, a.ld, a.ncols, blk0, rhs0, rhs1,
+                                true, nullptr, 0.0, nullptr, 0.0, acc, acc,
+                                out, out + a.slot2);
   if (a.ncols2 > 0)
-    sweep<T, RPL, CPT, 1, 0>((const T*)a.V2, a.ld, a.ncols2, blk0, cvalid,
-                             rhs[0], rhs[1], true, nullptr, 0.0, nullptr, 0.0,
-                             acc, acc, wacc, out + a.ncols, nullptr);
+    sweep<T, CPT, 1, 0>((const T*)a.V2, a.ld, a.ncols2, blk0, rhs0, rhs1, true,
+                        nullptr, 0.0, nullptr, 0.0, acc, acc, out + a.ncols,
+                        nullptr);
   if (a.want_ss) {
+    // sum of squares over the workgroup's rows, once per row
+    double ss = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int64_t i = blk0 + c * kChunkRows + tid;
+      double v = 0.0;
+      if (GEN)
+        v = g[c * kChunkRows + tid];
+      else if (i < a.n && i > a.lo)
+        v = (double)((const T*)a.b)[i];
+      ss += v * v;
+    }
     const double s = block_sum(ss, scr);
     if (tid == 0) out[a.extra + kSlotPFSS] = s;
   }
@@ -373,56 +507,52 @@ __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
 
 // ---------------------------------------------------------------- GEMV-N --
 
-template <typename T, int RPL, int CPT, int MODE>
+template <typename T, int CPT, int MODE>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
-  constexpr int kRows = kWG * RPL;
-  __shared__ double wacc[kWaves * kFlush];
+  __shared__ double gpf[CPT * kChunkRows];   // next draw (prefetch)
+  __shared__ double gcur[CPT * kChunkRows];  // this draw, or the new column
+  __shared__ double comb[kWaves * CPT * kChunkRows];
   __shared__ double scr[kWaves];
   const int tid = threadIdx.x;
   const int k = a.k;
-  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
+  const int64_t blk0 = (int64_t)blk * (kChunkRows * CPT);
   T* __restrict__ V = (T*)a.V;
   const PhiloxKey key{a.key.k0, a.key.k1};
-  double acc[CPT][RPL];
-  double gn[CPT][RPL];
-  bool cvalid[CPT];
-  double pfss = 0.0;
+  if (a.pf) draw_block<T, CPT>(key, a.pf_step, blk0, a.pf_cut, a.n, true, gpf);
+  if (MODE == kPassRandHaar)
+    draw_block<T, CPT>(key, a.step, blk0, (int64_t)k - 1, a.n, false, gcur);
+  __syncthreads();
+  double gn[CPT][4], acc[CPT][4];
 #pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kRows;
-    cvalid[c] = row0 < a.ld;
-    draw_rows<T, RPL>(key, a.pf_step, row0 + RPL * tid, a.pf_cut,
-                      (a.pf && cvalid[c]) ? a.n : 0, true, gn[c]);
+  for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int e = 0; e < RPL; ++e) {
+    for (int e = 0; e < 4; ++e) {
+      gn[c][e] = 0.0;
       acc[c][e] = 0.0;
-      pfss += gn[c][e] * gn[c][e];
     }
-  }
+  if (a.pf) lane_rows<CPT>(gpf, gn);
   double* out = a.partials + (int64_t)blk * a.pstride;
-  sweep<T, RPL, CPT, 1, 1>(V, a.ld, k, blk0, cvalid, gn, gn, a.pf != 0, a.z,
-                           1.0, nullptr, 0.0, acc, acc, wacc, out, nullptr);
+  sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, a.z, 1.0, nullptr,
+                      0.0, acc, acc, out, nullptr);
+  double vz[CPT];  // -(V z) for this thread's rows
+  combine_rows<CPT>(acc, comb, vz);
 
-  // Epilogue: form the output rows, write the new column k, and the extras.
-  double ssq = 0.0, pfnew = 0.0, ysq = 0.0;
-  double ur[CPT][RPL];  // stored rows > k of the new column (data mode)
+  // Epilogue, one row per thread and chunk: the output rows, the new column
+  // k, and the extras.
+  double ssq = 0.0, pfnew = 0.0, pfss = 0.0, ysq = 0.0;
   const double pik = a.pi[k];
   const double cs = (MODE == kPassRandHaar) ? *a.cscale : 0.0;
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    if (!cvalid[c]) continue;
-    const int64_t i0 = blk0 + (int64_t)c * kRows + RPL * tid;
-    double gt[RPL];
-    if (MODE == kPassRandHaar)
-      draw_rows<T, RPL>(key, a.step, i0, (int64_t)k - 1, a.n, false, gt);
-#pragma unroll
-    for (int e = 0; e < RPL; ++e) {
-      const int64_t i = i0 + e;
-      ur[c][e] = 0.0;
-      if (i >= a.n) continue;
+    const int q = c * kChunkRows + tid;
+    const int64_t i = blk0 + q;
+    const double gnext = a.pf ? gpf[q] : 0.0;
+    pfss += gnext * gnext;
+    double unew = 0.0;
+    if (i < a.n) {
       const double sg = (i < k) ? a.pi[i + 1] : pik;
       if (MODE == kPassData) {
-        const double p = sg * ((double)((const T*)a.x)[i] + acc[c][e]);
+        const double p = sg * ((double)((const T*)a.x)[i] + vz[c]);
         if (i < k) {
           a.head[i] = p;
         } else if (i == k) {
@@ -430,14 +560,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
         } else {
           const T ps = (T)p;
           V[(int64_t)k * a.ld + i] = ps;
-          const double pd = (double)ps;
-          ur[c][e] = pd;
-          ssq += pd * pd;
-          pfnew += pd * gn[c][e];
+          unew = (double)ps;
+          ssq += unew * unew;
+          pfnew += unew * gnext;
         }
       } else {
-        const double w = (i < k) ? a.head[i] : cs * gt[e];
-        const T ys = (T)(sg * w + acc[c][e]);
+        const double w = (i < k) ? a.head[i] : cs * gcur[q];
+        const T ys = (T)(sg * w + vz[c]);
         ((T*)a.y)[i] = ys;
         ysq += (double)ys * (double)ys;
         if (a.dyn.kind) {
@@ -448,25 +577,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
           ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
         }
         if (i > k) {
-          const T gs = (T)gt[e];
+          const T gs = (T)gcur[q];
           V[(int64_t)k * a.ld + i] = gs;
-          pfnew += (double)gs * gn[c][e];
+          pfnew += (double)gs * gnext;
         }
       }
     }
+    if (MODE == kPassData) gcur[q] = unew;
   }
   if (MODE == kPassData && a.cslot >= 0) {
     // dots of the earlier columns with the new one, for its T column (these
     // rows of V were just read, so they mostly come from L2)
-#pragma unroll
-    for (int c = 0; c < CPT; ++c)
-      if (!cvalid[c]) {
-#pragma unroll
-        for (int e = 0; e < RPL; ++e) ur[c][e] = 0.0;
-      }
-    sweep<T, RPL, CPT, 1, 0>(V, a.ld, k, blk0, cvalid, ur, ur, true, nullptr,
-                             0.0, nullptr, 0.0, acc, acc, wacc, out + a.cslot,
-                             nullptr);
+    __syncthreads();
+    double ur[CPT][4];
+    lane_rows<CPT>(gcur, ur);
+    sweep<T, CPT, 1, 0>(V, a.ld, k, blk0, ur, ur, true, nullptr, 0.0, nullptr,
+                        0.0, acc, acc, out + a.cslot, nullptr);
   }
   if (MODE == kPassData) {
     const double s = block_sum(ssq, scr);
@@ -487,155 +613,79 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
 
 // ------------------------------------------------- Ginibre random side --
 
-template <typename T, int RPL, int CPT>
+template <typename T, int CPT>
 __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
-  constexpr int kRows = kWG * RPL;
-  __shared__ double wacc[kWaves * kFlush];
+  __shared__ double gpf[CPT * kChunkRows];
+  __shared__ double gcur[CPT * kChunkRows];
+  __shared__ double comb[kWaves * CPT * kChunkRows];
   const int tid = threadIdx.x;
   const int k = a.k, nb = a.nb;
-  const int64_t blk0 = (int64_t)blk * (kRows * CPT);
+  const int64_t blk0 = (int64_t)blk * (kChunkRows * CPT);
   T* __restrict__ B = (T*)a.B;
   const PhiloxKey key{a.key.k0, a.key.k1};
-  double acc0[CPT][RPL], acc1[CPT][RPL], gn[CPT][RPL];
-  bool cvalid[CPT];
+  if (a.pf) draw_block<T, CPT>(key, a.pf_step, blk0, a.pf_cut, a.n, true, gpf);
+  draw_block<T, CPT>(key, a.step, blk0, (int64_t)k - 1, a.n, false, gcur);
+  __syncthreads();
+  double gn[CPT][4], acc0[CPT][4], acc1[CPT][4];
 #pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int64_t row0 = blk0 + (int64_t)c * kRows;
-    cvalid[c] = row0 < a.ld;
-    draw_rows<T, RPL>(key, a.pf_step, row0 + RPL * tid, a.pf_cut,
-                      (a.pf && cvalid[c]) ? a.n : 0, true, gn[c]);
+  for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int e = 0; e < RPL; ++e) {
+    for (int e = 0; e < 4; ++e) {
+      gn[c][e] = 0.0;
       acc0[c][e] = 0.0;
       acc1[c][e] = 0.0;
     }
-  }
+  if (a.pf) lane_rows<CPT>(gpf, gn);
   double* out = a.partials + (int64_t)blk * a.pstride;
   // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
   // and the prefetch dots
-  sweep<T, RPL, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, cvalid, gn, gn,
-                           a.pf != 0, a.z1, 1.0, a.z2, 1.0, acc0, acc1, wacc,
-                           out, nullptr);
+  sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, a.z1,
+                      1.0, a.z2, 1.0, acc0, acc1, out, nullptr);
   // explicit basis panel: acc1 += B c
   if (nb > 0)
-    sweep<T, RPL, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, cvalid, gn, gn,
-                             false, a.c, -1.0, nullptr, 0.0, acc1, acc1, wacc,
-                             nullptr, nullptr);
+    sweep<T, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, gn, gn, false, a.c, -1.0,
+                        nullptr, 0.0, acc1, acc1, nullptr, nullptr);
+  double u0[CPT], u1[CPT];
+  combine_rows<CPT>(acc0, comb, u0);
+  combine_rows<CPT>(acc1, comb, u1);
   const double nu = a.scal[0], sigma = a.scal[1];
   const double pik = a.pi[k];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
-    if (!cvalid[c]) continue;
-    const int64_t i0 = blk0 + (int64_t)c * kRows + RPL * tid;
-    double gt[RPL];
-    draw_rows<T, RPL>(key, a.step, i0, (int64_t)k - 1, a.n, false, gt);
-#pragma unroll
-    for (int e = 0; e < RPL; ++e) {
-      const int64_t i = i0 + e;
-      if (i >= a.n) continue;
-      const double sg = (i < k) ? a.pi[i + 1] : pik;
-      const double gi = gt[e];
-      B[(int64_t)nb * a.ld + i] = (T)(sg * gi + acc0[c][e]);
-      const double hv = (i < k) ? a.h[i] : 0.0;
-      const T ys = (T)(sigma * (acc1[c][e] + sg * (hv + nu * gi)));
-      ((T*)a.y)[i] = ys;
-      if (a.dyn.kind) {
-        const double xi = (double)((const T*)a.dyn.x)[i];
-        const double xpi = a.dyn.kind == kDynSoftHist
-                               ? (double)((const T*)a.dyn.xprev)[i]
-                               : 0.0;
-        ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
-      }
+    const int q = c * kChunkRows + tid;
+    const int64_t i = blk0 + q;
+    if (i >= a.n) continue;
+    const double sg = (i < k) ? a.pi[i + 1] : pik;
+    const double gi = gcur[q];
+    B[(int64_t)nb * a.ld + i] = (T)(sg * gi + u0[c]);
+    const double hv = (i < k) ? a.h[i] : 0.0;
+    const T ys = (T)(sigma * (u1[c] + sg * (hv + nu * gi)));
+    ((T*)a.y)[i] = ys;
+    if (a.dyn.kind) {
+      const double xi = (double)((const T*)a.dyn.x)[i];
+      const double xpi = a.dyn.kind == kDynSoftHist
+                             ? (double)((const T*)a.dyn.xprev)[i]
+                             : 0.0;
+      ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
     }
   }
 }
 
 // ---------------------------------------------------- kernel wrappers ----
 
-template <typename T, int RPL, int CPT, bool GEN, bool TWO>
+template <typename T, int CPT, bool GEN, bool TWO>
 __global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
-  tdot_body<T, RPL, CPT, GEN, TWO>(a, blockIdx.x);
+  tdot_body<T, CPT, GEN, TWO>(a, blockIdx.x);
 }
 
-template <typename T, int RPL, int CPT, int MODE>
+template <typename T, int CPT, int MODE>
 __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
-  pass_body<T, RPL, CPT, MODE>(a, blockIdx.x);
+  pass_body<T, CPT, MODE>(a, blockIdx.x);
 }
 
-template <typename T, int RPL, int CPT>
+template <typename T, int CPT>
 __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
-  gin_pass_body<T, RPL, CPT>(a, blockIdx.x);
-}
-
-// Ring of three trajectory vectors of a batched trial, stride ld: x_t is
-// slot (t-1) % 3.
-template <typename T>
-__device__ __forceinline__ const T* ring_slot(const void* base, int64_t ld,
-                                              int slot) {
-  return (const T*)base + (int64_t)slot * ld;
-}
-
-template <typename T, int RPL, int CPT, bool GEN, bool TWO>
-__global__ __launch_bounds__(kWG) void k_tdot_batch(const TdotArgs* A,
-                                                    BatchMap bm, StepPatch p) {
-  const int trial = bm.blk_trial[blockIdx.x];
-  TdotArgs a = A[trial];
-  a.ncols = p.k;
-  if (GEN) {
-    a.gen_step = p.step;
-    a.lo = p.k;
-    a.want_ss = p.want_ss;
-  } else {
-    a.b = ring_slot<T>(a.b, a.ld, (int)((p.step - 1) % 3));
-    a.b2 = TWO ? (const void*)((const T*)a.V + (int64_t)p.kp * a.ld) : nullptr;
-  }
-  tdot_body<T, RPL, CPT, GEN, TWO>(a, blockIdx.x - bm.blk_first[trial]);
-}
-
-template <typename T, int RPL, int CPT, int MODE>
-__global__ __launch_bounds__(kWG) void k_pass_batch(const PassArgs* A,
-                                                    BatchMap bm, StepPatch p) {
-  const int trial = bm.blk_trial[blockIdx.x];
-  PassArgs a = A[trial];
-  a.k = p.k;
-  a.step = p.step;
-  a.pf = p.pf;
-  a.pf_step = p.step + 1;
-  a.pf_cut = p.k + 1;
-  if (MODE == kPassData) a.x = ring_slot<T>(a.x, a.ld, (int)((p.step - 1) % 3));
-  if (a.dyn.kind) {
-    // dyn.x holds the ring base: x_t, x_{t-1}, x_{t+1} are its slots
-    const void* ring = a.dyn.x;
-    a.dyn.x = ring_slot<T>(ring, a.ld, (int)((p.step - 1) % 3));
-    a.dyn.xprev = ring_slot<T>(ring, a.ld, (int)((p.step + 1) % 3));
-    a.dyn.xnext = (void*)ring_slot<T>(ring, a.ld, (int)(p.step % 3));
-  }
-  pass_body<T, RPL, CPT, MODE>(a, blockIdx.x - bm.blk_first[trial]);
-}
-
-// One workgroup per trial: fixed-order sums of the trial's partial rows,
-// then the trial's small FP64 step.
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_trial_small(int op,
-                                                     const TrialSums* sums,
-                                                     SlotRanges rg,
-                                                     const SmallDataArgs* sd,
-                                                     const HaarSmallArgs* hs,
-                                                     StepPatch p) {
-  const int trial = blockIdx.x;
-  const TrialSums S = sums[trial];
-  reduce_rows(S.partials, S.pstride, 0, S.nwg, rg, S.out);
-  if (op == kTrialSmallData) {
-    SmallDataArgs a = sd[trial];
-    a.kp = p.kp;
-    a.k = p.k;
-    small_data_body(a);
-  } else if (op == kTrialHaarSmall) {
-    HaarSmallArgs a = hs[trial];
-    a.k = p.k;
-    a.step = p.step;
-    haar_small_body<T>(a);
-  }
+  gin_pass_body<T, CPT>(a, blockIdx.x);
 }
 
 // ------------------------------------------------- standalone kernels ----
@@ -724,26 +774,22 @@ __global__ __launch_bounds__(kWG) void k_fill(double* p, double v,
     if (e_ != hipSuccess) return (int)e_; \
   } while (0)
 
-// Launch shapes (rpl, cpt): (1,1) for small panels, (4, 1|2|4|8) otherwise.
-#define HD_DISPATCH_SHAPE(SH, KERNEL_T, ...)                                 \
-  do {                                                                       \
-    if ((SH).rpl == 1 && (SH).cpt == 1)                                      \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(1, 1)), __VA_ARGS__);      \
-    else if ((SH).rpl == 4 && (SH).cpt == 1)                                 \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 1)), __VA_ARGS__);      \
-    else if ((SH).rpl == 4 && (SH).cpt == 2)                                 \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 2)), __VA_ARGS__);      \
-    else if ((SH).rpl == 4 && (SH).cpt == 4)                                 \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 4)), __VA_ARGS__);      \
-    else if ((SH).rpl == 4 && (SH).cpt == 8)                                 \
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4, 8)), __VA_ARGS__);      \
-    else                                                                     \
-      return -1;                                                             \
+// Launch shapes: CPT = 1, 2 or 4 chunks of 256 rows per workgroup.
+#define HD_DISPATCH_SHAPE(SH, KERNEL_T, ...)                            \
+  do {                                                                  \
+    if ((SH).cpt == 1)                                                  \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(1)), __VA_ARGS__);    \
+    else if ((SH).cpt == 2)                                             \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(2)), __VA_ARGS__);    \
+    else if ((SH).cpt == 4)                                             \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(KERNEL_T(4)), __VA_ARGS__);    \
+    else                                                                \
+      return -1;                                                        \
   } while (0)
 
 template <typename T, bool GEN, bool TWO>
 static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s) {
-#define K_(R, C) k_tdot<T, R, C, GEN, TWO>
+#define K_(C) k_tdot<T, C, GEN, TWO>
   HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
 #undef K_
   HD_CHECK_LAUNCH();
@@ -761,34 +807,9 @@ int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s) {
   return f64 ? tdot_t<double>(sh, a, s) : tdot_t<float>(sh, a, s);
 }
 
-template <typename T, bool GEN, bool TWO>
-static int tdot_batch_shape(Shape sh, const TdotArgs* A, BatchMap bm,
-                            StepPatch p, hipStream_t s) {
-#define K_(R, C) k_tdot_batch<T, R, C, GEN, TWO>
-  HD_DISPATCH_SHAPE(sh, K_, dim3(bm.nblk), dim3(kWG), 0, s, A, bm, p);
-#undef K_
-  HD_CHECK_LAUNCH();
-  return 0;
-}
-
-template <typename T>
-static int tdot_batch_t(Shape sh, const TdotArgs* A, BatchMap bm, StepPatch p,
-                        int gen, hipStream_t s) {
-  if (gen) return tdot_batch_shape<T, true, false>(sh, A, bm, p, s);
-  if (p.kp > 0) return tdot_batch_shape<T, false, true>(sh, A, bm, p, s);
-  return tdot_batch_shape<T, false, false>(sh, A, bm, p, s);
-}
-
-int launch_tdot_batch(int f64, Shape sh, const TdotArgs* args, BatchMap bm,
-                      StepPatch p, int gen, hipStream_t s) {
-  if (bm.nblk <= 0) return 0;
-  return f64 ? tdot_batch_t<double>(sh, args, bm, p, gen, s)
-             : tdot_batch_t<float>(sh, args, bm, p, gen, s);
-}
-
 template <typename T, int MODE>
 static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s) {
-#define K_(R, C) k_pass<T, R, C, MODE>
+#define K_(C) k_pass<T, C, MODE>
   HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
 #undef K_
   HD_CHECK_LAUNCH();
@@ -804,31 +825,9 @@ int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                            : pass_shape<float, kPassRandHaar>(sh, a, s);
 }
 
-template <typename T, int MODE>
-static int pass_batch_shape(Shape sh, const PassArgs* A, BatchMap bm,
-                            StepPatch p, hipStream_t s) {
-#define K_(R, C) k_pass_batch<T, R, C, MODE>
-  HD_DISPATCH_SHAPE(sh, K_, dim3(bm.nblk), dim3(kWG), 0, s, A, bm, p);
-#undef K_
-  HD_CHECK_LAUNCH();
-  return 0;
-}
-
-int launch_pass_batch(int f64, Shape sh, int mode, const PassArgs* args,
-                      BatchMap bm, StepPatch p, hipStream_t s) {
-  if (bm.nblk <= 0) return 0;
-  if (f64)
-    return mode == kPassData
-               ? pass_batch_shape<double, kPassData>(sh, args, bm, p, s)
-               : pass_batch_shape<double, kPassRandHaar>(sh, args, bm, p, s);
-  return mode == kPassData
-             ? pass_batch_shape<float, kPassData>(sh, args, bm, p, s)
-             : pass_batch_shape<float, kPassRandHaar>(sh, args, bm, p, s);
-}
-
 template <typename T>
 static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
-#define K_(R, C) k_gin_pass<T, R, C>
+#define K_(C) k_gin_pass<T, C>
   HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
 #undef K_
   HD_CHECK_LAUNCH();
@@ -837,20 +836,6 @@ static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
 
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s) {
   return f64 ? gin_shape<double>(sh, a, s) : gin_shape<float>(sh, a, s);
-}
-
-int launch_trial_small(int f64, int op, int ntrials, const TrialSums* sums,
-                       SlotRanges rg, const SmallDataArgs* sd,
-                       const HaarSmallArgs* hs, StepPatch p, hipStream_t s) {
-  if (ntrials <= 0) return 0;
-  if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<double>), dim3(ntrials),
-                       dim3(kWG), 0, s, op, sums, rg, sd, hs, p);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<float>), dim3(ntrials),
-                       dim3(kWG), 0, s, op, sums, rg, sd, hs, p);
-  HD_CHECK_LAUNCH();
-  return 0;
 }
 
 int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s) {
