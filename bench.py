@@ -18,6 +18,11 @@ Workloads (--workload):
       x_0 = 0; FP32 panels and vectors, FP64 accumulation, norms and T.
   c1  Haar n = 1000, T = 20, FP64; x_{t+1} = tanh(y_t) + 0.5 x_t,
       x_1 ~ N(0, I/n).
+  c3  4096 independent Haar trials, n log-uniform in [1e3, 1e5], T uniform
+      in [10, 200] (tag-5 draws), x_{t+1} = tanh(2 y_t), x_1 ~ N(0, I/n),
+      FP32, all trials in one batch (hd_batch_run); a step runs every trial
+      to completion.  Also times the same kind of trials one handle at a time
+      (a sample of them) for the batched-vs-plain comparison.
 """
 import argparse
 import json
@@ -45,6 +50,10 @@ WORKLOADS = {
                T=20, dyn="tanh", a=1.0, b=0.5, pattern="Q", f64=True,
                x1_scale=None),
 }
+
+
+C3 = dict(name="haar_batch4096_n1e3-1e5_T10-200_tanh2_fp32", count=4096,
+          a=2.0, b=0.0, plain_sample=256)
 
 
 def nominal_work(n, T):
@@ -85,18 +94,93 @@ def cpu_baseline(wl, budget_s=15.0):
                        % (done, trial, dt))
 
 
+def batch_bytes(n, T, es=4):
+    """Algorithmic bytes of one Haar trial, per query with k = t-1 reflectors
+    per side: TDOT (k columns + x + the pending column), data pass (k columns
+    + x + the new column), random pass (k columns + y + the new column + x_t
+    read and x_{t+1} written by the fused map)."""
+    k = np.arange(T, dtype=np.float64)
+    return float(es * np.sum(3.0 * n * k + 8.0 * n))
+
+
+def main_batch(args):
+    import torch
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import inputs
+    dev = "cuda:0"
+    nb, Tb = inputs.ragged_batch(C3["count"])
+    trials = [(int(n), int(T), 0, b) for b, (n, T) in enumerate(zip(nb, Tb))]
+    x1 = [torch.from_numpy(inputs.x1_normal(n, seed=0, trial=b)).to(
+        dev, torch.float32) for n, T, _, b in trials]
+    W = float(sum(nominal_work(n, T) for n, T, _, _ in trials))
+    by = sum(batch_bytes(n, T) for n, T, _, _ in trials)
+    B = hd.HaarBatch(trials, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        B.run(x1, "tanh", C3["a"], C3["b"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.run(x1, "tanh", C3["a"], C3["b"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if B.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    del B
+    # plain: a sample of the same trials, one handle and hd_run each
+    rs = np.random.default_rng(7).choice(len(trials), C3["plain_sample"],
+                                         replace=False)
+    Ws, tp = 0.0, 0.0
+    for i in rs:
+        n, T, s, k = trials[i]
+        A = hd.LazyMatrix(hd.HAAR, n, t_max=T, seed=s, trial=k, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()   # the run only, not the allocation
+        A.run(x1[i], T, "tanh", C3["a"], C3["b"], record=False)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t1
+        Ws += nominal_work(n, T)
+        del A
+    plain = Ws / tp
+    value = W * args.steps / elapsed
+    gbs = by * args.steps / elapsed / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "elem-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": C3["name"], "trials": len(trials),
+                   "elem_updates_per_step": W,
+                   "algorithmic_bytes_per_step": by},
+        "roofline": {"bound": "hbm", "kernel": "whole batched step",
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "plain_per_trial": {"value": plain, "unit": "elem-updates/s",
+                            "sample": "%d of the trials, one handle each "
+                                      "(hd_run), plan with the same kernels"
+                                      % len(rs)},
+        "batched_vs_plain": value / plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2",
+                    choices=sorted(list(WORKLOADS) + ["c3"]))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
               "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3":
+        main_batch(args)
+        return
 
     import torch
     import paper_2101_07464_amd as hd

@@ -141,6 +141,59 @@ int hd_profile(hd_handle h, int32_t enable);
 int hd_profile_read(hd_handle h, int32_t kind, double* ms, int64_t* launches,
                     double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent Haar trials.
+ *
+ * Many independent trials of eq. (dynamics) with Haar Q (Alg. 2), each with
+ * its own n, number of queries T and Philox key (seed, trial), all with
+ * M_t = Q and the same built-in f_t, run to completion together: the trials
+ * advance in lockstep one query index at a time and every launch covers all
+ * trials still running, so a step costs a handful of launches for the whole
+ * batch instead of for every trial.  Each trial's answers equal those of a
+ * separate handle with the same key (hd_run) up to the order of the FP64
+ * partial sums.
+ * ------------------------------------------------------------------------ */
+typedef struct hd_batch_ctx* hd_batch;
+
+typedef struct {
+  int64_t n;      /* dimension of the trial's Q (n x n), n >= 1 */
+  int32_t T;      /* queries of the trial, 1 <= T <= n */
+  uint32_t seed;  /* Philox key word 0 */
+  uint32_t trial; /* Philox key word 1 */
+} hd_batch_trial;
+
+/* Allocate the device state of `count` trials (storage HD_F32 or HD_F64) on
+ * `stream` (hipStream_t, NULL = null stream).  The handle owns one arena
+ * holding every trial's two panels (n rounded up to 1024 rows, T columns),
+ * FP64 scalars and work vectors.  The trial list is copied.
+ * Errors: HD_ERR_INVALID (count < 1, bad n or T, out == NULL),
+ * HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
+                  int32_t count, void* stream, hd_batch* out);
+
+/* Run every trial from a fresh Q (query 1) to its own T with the built-in map
+ * dyn->kind (HD_DYN_TANH or HD_DYN_SOFT_HIST; dyn->pattern must be
+ * HD_PATTERN_Q; x_0 = 0).  x1: host array of `count` device pointers, x_1 of
+ * each trial (n_i entries), in the order given to hd_batch_init.  x_out: NULL
+ * or host array of device pointers receiving x_{T_i+1}.  traj_x / traj_y:
+ * NULL or host arrays of device pointers to (T_i+1) x n_i and T_i x n_i
+ * row-major buffers receiving x_1..x_{T_i+1} and y_1..y_{T_i}.  Each call
+ * starts the trials over with the same keys.  Stream-ordered; the pointer
+ * arrays are read before the call returns.
+ * Errors: HD_ERR_INVALID, HD_ERR_UNSUPPORTED (other maps or patterns),
+ * HD_ERR_HIP. */
+int hd_batch_run(hd_batch b, const hd_dynamics* dyn, const void* const* x1,
+                 void* const* x_out, void* const* traj_x, void* const* traj_y);
+
+/* Synchronise and report the sticky device flag (as hd_status). */
+int hd_batch_status(hd_batch b);
+
+/* Change the stream of later calls. */
+int hd_batch_set_stream(hd_batch b, void* stream);
+
+/* Release the batch after its stream has drained.  NULL is a no-op. */
+int hd_batch_free(hd_batch b);
+
 /* Message for an HD_* code (static storage). */
 const char* hd_strerror(int code);
 

@@ -178,3 +178,73 @@ class LazyMatrix:
                                                ctypes.byref(by)),
                    "hd_profile_read")
         return ms.value, cnt.value, by.value
+
+
+class HaarBatch:
+    """Independent Haar trials run together (all Q-queries, one built-in f_t).
+
+    trials: list of (n, T, seed, trial) tuples.  run() starts every trial
+    from a fresh Q and returns, per trial in the given order, x_{T+1}, or the
+    recorded (X, Y) trajectories when record is True.
+    """
+
+    def __init__(self, trials, dtype=None, device="cuda:0"):
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be float32 or float64")
+        self.trials = [tuple(int(v) for v in t) for t in trials]
+        self.dtype = dtype
+        self.device = torch.device(device)
+        arr = (_lib.HDBatchTrial * len(self.trials))(
+            *[_lib.HDBatchTrial(n, T, s, k) for n, T, s, k in self.trials])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().hd_batch_init(
+                HD_F64 if dtype == torch.float64 else HD_F32, arr,
+                len(self.trials), _stream_ptr(self.device), ctypes.byref(h)),
+                "hd_batch_init")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().hd_batch_free(h)
+            self._h = None
+
+    def _ptrs(self, tensors):
+        return (ctypes.c_void_p * len(tensors))(
+            *[t.data_ptr() for t in tensors])
+
+    def run(self, x1, dyn, a, b, record=False):
+        """x1: list of device tensors (n_i entries each)."""
+        torch = _torch()
+        if len(x1) != len(self.trials):
+            raise ValueError("one x1 per trial")
+        x1 = [t.to(self.device, self.dtype).contiguous() for t in x1]
+        for t, (n, _, _, _) in zip(x1, self.trials):
+            if t.numel() != n:
+                raise ValueError("x1 length does not match the trial's n")
+        L = _lib.load()
+        _lib.check(L.hd_batch_set_stream(self._h, _stream_ptr(self.device)),
+                   "hd_batch_set_stream")
+        d = _lib.HDDynamics(_DYN[dyn], HD_PATTERN_Q, a, b)
+        if record:
+            X = [torch.empty((T + 1, n), dtype=self.dtype, device=self.device)
+                 for n, T, _, _ in self.trials]
+            Y = [torch.empty((T, n), dtype=self.dtype, device=self.device)
+                 for n, T, _, _ in self.trials]
+            _lib.check(L.hd_batch_run(self._h, ctypes.byref(d),
+                                      self._ptrs(x1), None, self._ptrs(X),
+                                      self._ptrs(Y)), "hd_batch_run")
+            return X, Y
+        out = [torch.empty(n, dtype=self.dtype, device=self.device)
+               for n, _, _, _ in self.trials]
+        _lib.check(L.hd_batch_run(self._h, ctypes.byref(d), self._ptrs(x1),
+                                  self._ptrs(out), None, None),
+                   "hd_batch_run")
+        self._keep = (x1, out)
+        return out
+
+    def status(self):
+        return _lib.load().hd_batch_status(self._h)

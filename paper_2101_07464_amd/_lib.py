@@ -31,7 +31,9 @@ HD_PATTERN_ALT = 1
 
 EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_counts", "hd_reset", "hd_set_stream", "hd_pivots", "hd_run",
-           "hd_profile", "hd_profile_read", "hd_strerror"]
+           "hd_profile", "hd_profile_read", "hd_strerror",
+           "hd_batch_init", "hd_batch_run", "hd_batch_status",
+           "hd_batch_set_stream", "hd_batch_free"]
 
 
 class HDConfig(ctypes.Structure):
@@ -45,6 +47,11 @@ class HDConfig(ctypes.Structure):
 class HDDynamics(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("pattern", ctypes.c_int32),
                 ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class HDBatchTrial(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("T", ctypes.c_int32),
+                ("seed", ctypes.c_uint32), ("trial", ctypes.c_uint32)]
 
 
 class HDError(RuntimeError):
@@ -85,6 +92,12 @@ def load():
         "hd_profile": (i32, [vp, i32]),
         "hd_profile_read": (i32, [vp, i32, P(dbl), P(i64), P(dbl)]),
         "hd_strerror": (ctypes.c_char_p, [i32]),
+        "hd_batch_init": (i32, [i32, P(HDBatchTrial), i32, vp, P(vp)]),
+        "hd_batch_run": (i32, [vp, P(HDDynamics), P(vp), P(vp), P(vp),
+                               P(vp)]),
+        "hd_batch_status": (i32, [vp]),
+        "hd_batch_set_stream": (i32, [vp, vp]),
+        "hd_batch_free": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

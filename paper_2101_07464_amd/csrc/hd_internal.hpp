@@ -213,6 +213,62 @@ struct Shape {
   int nwg;
 };
 
+// ------------------------------------------------------------- batches --
+//
+// Many independent Haar trials advance in lockstep, one query index at a
+// time, all Q-queries.  Trials are sorted by their number of steps (longest
+// first), so the trials still running at a step are a prefix of the list and
+// their workgroups a prefix of the block map.  Every workgroup covers 256 rows
+// and the same number of columns, whatever its trial.
+
+// Per-trial arguments in device memory; the per-step fields are patched by
+// the batched kernels.
+struct TrialDev {
+  TdotArgs td;        // data-side TDOT (partials = the trial's partial rows)
+  PassArgs pd;        // data pass
+  PassArgs pr;        // random pass (partials = the trial's second buffer)
+  SmallDataArgs sd;
+  HaarSmallArgs hs;
+  const void* xbase;  // x_t at xbase + ((t - 1) % xmod) * n elements
+  int xmod;
+  void* ybase;        // y_t at ybase + ((t - 1) % ymod) * n elements
+  int ymod;
+  const void* x0;     // x_0 (zeros)
+  int T;              // queries of the trial
+  int nwg;            // workgroups of its panels
+};
+
+struct BatchMap {
+  const int* blk_trial;  // trial of each workgroup
+  const int* blk_first;  // first workgroup of each trial
+};
+
+struct BatchStep {
+  int k;          // reflectors per panel before this query (step - 1)
+  uint32_t step;  // 1-based query index
+};
+
+enum BatchSmallOp { kBatchAfterTdot = 0, kBatchAfterData = 1 };
+
+int launch_tdot_batch(int f64, int cpt, int nblk, int two, const TrialDev* d,
+                      BatchMap m, BatchStep st, hipStream_t s);
+int launch_pass_batch(int f64, int cpt, int nblk, int mode, const TrialDev* d,
+                      BatchMap m, BatchStep st, hipStream_t s);
+int launch_trial_small(int f64, int op, int ntrials, const TrialDev* d,
+                       BatchStep st, hipStream_t s);
+// Query 1 of every trial: ||g_1[1:]||^2 of the random side into the second
+// partial buffer (the prefetch a previous query would have left there).
+int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
+                           BatchMap m, hipStream_t s);
+
+// Device-to-device copies of 4-byte words, one workgroup per job.
+struct CopyJob {
+  const void* src;
+  void* dst;
+  int64_t words;
+};
+int launch_copy_jobs(const CopyJob* jobs, int count, hipStream_t s);
+
 int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s);
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
                 hipStream_t s);

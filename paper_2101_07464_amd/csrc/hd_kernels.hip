@@ -688,6 +688,137 @@ __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
   gin_pass_body<T, CPT>(a, blockIdx.x);
 }
 
+// ------------------------------------------------------- batched kernels --
+
+template <typename T>
+__device__ __forceinline__ const T* batch_vec(const void* base, int mod,
+                                              int64_t n, int64_t t) {
+  return (const T*)base + ((t - 1) % mod) * n;
+}
+
+template <typename T, int CPT, bool TWO>
+__global__ __launch_bounds__(kWG) void k_tdot_batch(const TrialDev* D,
+                                                    BatchMap m, BatchStep st) {
+  const int trial = m.blk_trial[blockIdx.x];
+  const TrialDev& d = D[trial];
+  TdotArgs a = d.td;
+  a.ncols = st.k;
+  a.b = batch_vec<T>(d.xbase, d.xmod, a.n, st.step);
+  // the column made by the previous query still needs its T column
+  a.b2 = TWO ? (const void*)((const T*)a.V + (int64_t)(st.k - 1) * a.ld)
+             : nullptr;
+  tdot_body<T, CPT, false, TWO>(a, blockIdx.x - m.blk_first[trial]);
+}
+
+template <typename T, int CPT, int MODE>
+__global__ __launch_bounds__(kWG) void k_pass_batch(const TrialDev* D,
+                                                    BatchMap m, BatchStep st) {
+  const int trial = m.blk_trial[blockIdx.x];
+  const TrialDev& d = D[trial];
+  PassArgs a = MODE == kPassData ? d.pd : d.pr;
+  const int64_t n = a.n, t = st.step;
+  a.k = st.k;
+  a.step = st.step;
+  if (MODE == kPassData) {
+    a.x = batch_vec<T>(d.xbase, d.xmod, n, t);
+  } else {
+    a.y = (void*)batch_vec<T>(d.ybase, d.ymod, n, t);
+    a.pf = (int)st.step < d.T;
+    a.pf_step = st.step + 1;
+    a.pf_cut = st.k + 1;
+    if (a.dyn.kind) {
+      a.dyn.x = batch_vec<T>(d.xbase, d.xmod, n, t);
+      a.dyn.xprev = t == 1 ? d.x0 : batch_vec<T>(d.xbase, d.xmod, n, t - 1);
+      a.dyn.xnext = (void*)batch_vec<T>(d.xbase, d.xmod, n, t + 1);
+    }
+  }
+  pass_body<T, CPT, MODE>(a, blockIdx.x - m.blk_first[trial]);
+}
+
+template <typename T, int CPT>
+__global__ __launch_bounds__(kWG) void k_prefetch1_batch(const TrialDev* D,
+                                                         BatchMap m) {
+  const int trial = m.blk_trial[blockIdx.x];
+  const PassArgs& pr = D[trial].pr;
+  TdotArgs a{};
+  a.V = pr.V;
+  a.ld = pr.ld;
+  a.gen = 1;
+  a.key = pr.key;
+  a.gen_step = 1;
+  a.lo = 0;
+  a.n = pr.n;
+  a.want_ss = 1;
+  a.partials = pr.partials;
+  a.pstride = pr.pstride;
+  a.extra = pr.extra;
+  tdot_body<T, CPT, true, false>(a, blockIdx.x - m.blk_first[trial]);
+}
+
+__global__ __launch_bounds__(kWG) void k_copy_jobs(const CopyJob* jobs) {
+  const CopyJob j = jobs[blockIdx.x];
+  const uint32_t* __restrict__ src = (const uint32_t*)j.src;
+  uint32_t* __restrict__ dst = (uint32_t*)j.dst;
+  for (int64_t i = threadIdx.x; i < j.words; i += kWG) dst[i] = src[i];
+}
+
+// One workgroup per running trial: the fixed-order sums of its partial rows
+// (workgroup-wide, several threads per slot), then its small step.
+//   after the TDOT: w (k slots), the previous query's T-column dots, and the
+//     previous random pass's prefetch dots and ||g||^2; then T column k-1 and
+//     z = T' w;
+//   after the data pass: ||p[k+1:]||^2; then the reflector scalars of both
+//     sides and the random side's coefficients.
+__device__ __forceinline__ void wg_reduce(const double* P, int pstride,
+                                          int nrows, int s0, int count,
+                                          double* out, double* lds) {
+  wg_sums<1>(
+      count, [](int) { return 0; }, [nrows](int) { return nrows; },
+      [=](int r, int j, double& t0, double& t1) {
+        t0 = P[(int64_t)r * pstride + s0 + j];
+        t1 = 0.0;
+      },
+      [=](int j, double v, double) { out[s0 + j] = v; }, lds);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kWG) void k_trial_small(const TrialDev* D,
+                                                     BatchStep st) {
+  __shared__ double lds[2 * kWG];
+  const TrialDev& d = D[blockIdx.x];
+  const int k = st.k;
+  if (OP == kBatchAfterTdot) {
+    const TdotArgs& td = d.td;
+    wg_reduce(td.partials, td.pstride, d.nwg, 0, k, (double*)d.sd.w, lds);
+    const int kp = k - 1;
+    if (kp > 0)
+      wg_reduce(td.partials, td.pstride, d.nwg, td.slot2, kp,
+                (double*)d.sd.w, lds);
+    {
+      // prefetch of the previous random pass (or of the query-1 kernel):
+      // k dots and the extras
+      const PassArgs& pr = d.pr;
+      wg_reduce(pr.partials, pr.pstride, d.nwg, 0, k, d.hs.G.red, lds);
+      wg_reduce(pr.partials, pr.pstride, d.nwg, pr.extra, kNumExtra,
+                d.hs.G.red, lds);
+    }
+    SmallDataArgs a = d.sd;
+    a.kp = kp;
+    a.c = d.sd.w + td.slot2;
+    a.k = k;
+    if (kp > 0 || k > 0) small_data_body(a);
+  } else {
+    const PassArgs& pd = d.pd;
+    wg_reduce(pd.partials, pd.pstride, d.nwg, pd.extra, kNumExtra, d.hs.D.red,
+              lds);
+    HaarSmallArgs a = d.hs;
+    a.k = k;
+    a.step = st.step;
+    a.cslot = -1;
+    haar_small_body<T>(a);
+  }
+}
+
 // ------------------------------------------------- standalone kernels ----
 
 __device__ __forceinline__ int slot_of(const SlotRanges& rg, int b) {
@@ -836,6 +967,110 @@ static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
 
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s) {
   return f64 ? gin_shape<double>(sh, a, s) : gin_shape<float>(sh, a, s);
+}
+
+int launch_tdot_batch(int f64, int cpt, int nblk, int two, const TrialDev* d,
+                      BatchMap m, BatchStep st, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  Shape sh{cpt, nblk};
+  if (f64) {
+    if (two) {
+#define K_(C) k_tdot_batch<double, C, true>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    } else {
+#define K_(C) k_tdot_batch<double, C, false>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    }
+  } else {
+    if (two) {
+#define K_(C) k_tdot_batch<float, C, true>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    } else {
+#define K_(C) k_tdot_batch<float, C, false>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    }
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_pass_batch(int f64, int cpt, int nblk, int mode, const TrialDev* d,
+                      BatchMap m, BatchStep st, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  Shape sh{cpt, nblk};
+  if (f64) {
+    if (mode == kPassData) {
+#define K_(C) k_pass_batch<double, C, kPassData>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    } else {
+#define K_(C) k_pass_batch<double, C, kPassRandHaar>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    }
+  } else {
+    if (mode == kPassData) {
+#define K_(C) k_pass_batch<float, C, kPassData>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    } else {
+#define K_(C) k_pass_batch<float, C, kPassRandHaar>
+      HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m, st);
+#undef K_
+    }
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_trial_small(int f64, int op, int ntrials, const TrialDev* d,
+                       BatchStep st, hipStream_t s) {
+  if (ntrials <= 0) return 0;
+  if (op == kBatchAfterTdot) {
+    if (f64)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<double, kBatchAfterTdot>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, st);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<float, kBatchAfterTdot>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, st);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<double, kBatchAfterData>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, st);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trial_small<float, kBatchAfterData>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, st);
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
+                           BatchMap m, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  Shape sh{cpt, nblk};
+  if (f64) {
+#define K_(C) k_prefetch1_batch<double, C>
+    HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m);
+#undef K_
+  } else {
+#define K_(C) k_prefetch1_batch<float, C>
+    HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m);
+#undef K_
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_copy_jobs(const CopyJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(k_copy_jobs, dim3(count), dim3(kWG), 0, s, jobs);
+  HD_CHECK_LAUNCH();
+  return 0;
 }
 
 int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s) {
