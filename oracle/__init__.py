@@ -222,3 +222,57 @@ def replay(orc, xs, transposes):
     """Mode B: answer the given query vectors in order; returns the outputs."""
     return [orc.query(np.asarray(x, np.float64), bool(tr))
             for x, tr in zip(xs, transposes)]
+
+
+# ---------------------------------------------------------------------
+# Unrolled ISTA with learned per-layer step and threshold, and its
+# gradient with the lazy matrix held fixed.
+#
+# Layer t (eq. (ista) with tau -> a_t and lambda tau -> theta_t):
+#     u_t = Q'(y - Q x_t),  v_t = x_t + a_t u_t,  x_{t+1} = eta_{theta_t}(v_t).
+# Every product with Q or Q' is a query on the same lazy matrix, so Q is one
+# fixed (if partly unrevealed) matrix throughout; the backward pass below is
+# plain reverse-mode calculus for that fixed Q, whose two matrix products per
+# layer are further queries.
+# ---------------------------------------------------------------------
+
+def lista_forward(orc, x1, y, a, theta):
+    """Layers t = 1..L (L = len(a)); returns X (L+1 rows, X[0] = x1),
+    U (L rows, u_t) and V (L rows, v_t).  2L queries: Q x_t, then Q'(.)."""
+    x = np.asarray(x1, np.float64)
+    y = np.asarray(y, np.float64)
+    X, U, V = [x], [], []
+    for at, th in zip(a, theta):
+        r = orc.query(x, False)
+        u = orc.query(y - r, True)
+        v = x + at * u
+        x = soft_threshold(v, th)
+        X.append(x)
+        U.append(u)
+        V.append(v)
+    return np.array(X), np.array(U), np.array(V)
+
+
+def lista_backward(orc, g, a, theta, U, V, need_x1=False):
+    """Reverse pass for dL/dx_{L+1} = g.  With the threshold mask
+    m_t = [|v_t| > theta_t]:
+        dL/dtheta_t = -sum(g * sign(v_t) * m_t),
+        gbar = g * m_t,  dL/da_t = sum(gbar * u_t),
+        dL/dx_t = gbar - a_t Q'Q gbar   (two queries: Q gbar, then Q'(.)).
+    The last product (t = 1) runs only when need_x1.  Returns
+    (da, dtheta, dL/dx_1 or None)."""
+    L = len(a)
+    g = np.asarray(g, np.float64)
+    da = np.zeros(L)
+    dth = np.zeros(L)
+    for t in range(L - 1, -1, -1):
+        m = np.abs(V[t]) > theta[t]
+        dth[t] = -np.sum(g * np.sign(V[t]) * m)
+        gbar = g * m
+        da[t] = np.sum(gbar * U[t])
+        if t == 0 and not need_x1:
+            return da, dth, None
+        q = orc.query(gbar, False)
+        w = orc.query(q, True)
+        g = gbar - a[t] * w
+    return da, dth, g

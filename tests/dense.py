@@ -33,3 +33,24 @@ def r_factor_positive(X):
     sg = np.sign(np.diag(Rm))
     sg[sg == 0] = 1.0
     return Rm * sg[:, None]
+
+
+def ginibre_rec(orc, m, n, sigma, W):
+    """Dense Q consistent with every answer the lazy Gaussian matrix gave
+    (eq. (Gaussian_t)): sigma (sum_i u_i v_i' + L_1..L_l Z W Z R_r..R_1) for
+    an arbitrary m x n matrix W."""
+    from oracle import SIDE_L, SIDE_R
+    t, r, l = orc.counts()
+    S = np.zeros((m, n))
+    for i in range(1, t + 1):
+        u, v = orc.basis(i)
+        S += np.outer(u, v)
+    Lm = np.eye(m)
+    for i in range(1, l + 1):
+        Lm = Lm @ reflector_matrix(m, orc.reflector(SIDE_L, i))
+    Rm = np.eye(n)
+    for i in range(1, r + 1):
+        Rm = reflector_matrix(n, orc.reflector(SIDE_R, i)) @ Rm
+    Zl = np.diag(np.r_[np.zeros(l), np.ones(m - l)])
+    Zr = np.diag(np.r_[np.zeros(r), np.ones(n - r)])
+    return sigma * (S + Lm @ Zl @ W @ Zr @ Rm)
