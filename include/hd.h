@@ -129,6 +129,39 @@ typedef struct {
 int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
            const void* x0, void* x_out, void* traj_x, void* traj_y);
 
+/* ------------------------------------------------------------------------
+ * Unrolled ISTA with learned per-layer parameters, and its gradient.
+ *
+ * Layer t = 1..L is the ISTA step of eq. (ista) with the step tau replaced
+ * by a_t and the threshold lambda tau by theta_t:
+ *     u_t = Q'(y - Q x_t),  v_t = x_t + a_t u_t,  x_{t+1} = eta_{theta_t}(v_t)
+ * (eta the element-wise soft threshold).  Every product with Q or Q' is a
+ * query on this handle, so all layers, and the reverse pass, see one fixed
+ * matrix Q: the reverse pass is the exact gradient of the unrolled map for
+ * that Q, and its own products with Q are further queries (Q'Q gbar per
+ * layer), revealing randomness as needed.
+ * ------------------------------------------------------------------------ */
+
+/* Forward pass, 2L queries (Q then Q' per layer).  a, theta: host arrays of
+ * L floats.  yobs: device, m entries.  X: device (L+1) x n row-major, row 0
+ * holds x_1 on entry, rows 1..L receive x_2..x_{L+1}.  U, V: device L x n,
+ * receive u_t and v_t (kept for the reverse pass).
+ * Errors: HD_ERR_INVALID, HD_ERR_CAPACITY (checked before any query: t_max,
+ * and for Ginibre r <= n, l <= m), HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_lista_forward(hd_handle h, int32_t L, const float* a,
+                     const float* theta, const void* yobs, void* X, void* U,
+                     void* V);
+
+/* Reverse pass for g = dL/dx_{L+1} (device, n entries), with U, V from the
+ * forward pass and the same a, theta.  grad_a, grad_theta: device arrays of
+ * L doubles receiving dL/da_t and dL/dtheta_t (threshold derivative taken as
+ * the indicator of |v| > theta).  g_x1: NULL, or device n entries receiving
+ * dL/dx_1.  Uses 2(L-1) queries (2L with g_x1).  Errors as the forward. */
+int hd_lista_backward(hd_handle h, int32_t L, const float* a,
+                      const float* theta, const void* U, const void* V,
+                      const void* g, double* grad_a, double* grad_theta,
+                      void* g_x1);
+
 /* Timing of the panel kernels with HIP events on the handle's stream.
  * hd_profile(h, 1) starts recording (clears previous records), 0 stops. */
 int hd_profile(hd_handle h, int32_t enable);

@@ -135,6 +135,46 @@ class LazyMatrix:
         _lib.check(rc, "hd_run")
         return xo, None
 
+    def lista_forward(self, a, theta, x1, y):
+        """Unrolled ISTA layers (see ``hd_lista_forward``): returns
+        X ((L+1) x n, X[0] = x1), U and V (L x n)."""
+        torch = _torch()
+        L = len(a)
+        af = (ctypes.c_float * L)(*[float(v) for v in a])
+        tf = (ctypes.c_float * L)(*[float(v) for v in theta])
+        X = torch.empty((L + 1, self.n), dtype=self.dtype, device=self.device)
+        X[0] = self._vec(x1, self.n)
+        U = torch.empty((L, self.n), dtype=self.dtype, device=self.device)
+        V = torch.empty((L, self.n), dtype=self.dtype, device=self.device)
+        y = self._vec(y, self.m)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_lista_forward(
+            self._h, L, af, tf, ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+            ctypes.c_void_p(V.data_ptr())), "hd_lista_forward")
+        return X, U, V
+
+    def lista_backward(self, a, theta, U, V, g, need_x1=False):
+        """Reverse pass: (dL/da, dL/dtheta as FP64 tensors, dL/dx_1 or
+        None) for g = dL/dx_{L+1}."""
+        torch = _torch()
+        L = len(a)
+        af = (ctypes.c_float * L)(*[float(v) for v in a])
+        tf = (ctypes.c_float * L)(*[float(v) for v in theta])
+        ga = torch.empty(L, dtype=torch.float64, device=self.device)
+        gt = torch.empty(L, dtype=torch.float64, device=self.device)
+        gx = (torch.empty(self.n, dtype=self.dtype, device=self.device)
+              if need_x1 else None)
+        g = self._vec(g, self.n)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_lista_backward(
+            self._h, L, af, tf, ctypes.c_void_p(U.data_ptr()),
+            ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+            ctypes.c_void_p(ga.data_ptr()), ctypes.c_void_p(gt.data_ptr()),
+            ctypes.c_void_p(gx.data_ptr()) if gx is not None else None),
+            "hd_lista_backward")
+        return ga, gt, gx
+
     def reset(self, seed, trial=0):
         """Restart with a fresh matrix keyed (seed, trial), same buffers."""
         _lib.check(_lib.load().hd_reset(self._h, seed, trial), "hd_reset")
@@ -248,3 +288,44 @@ class HaarBatch:
 
     def status(self):
         return _lib.load().hd_batch_status(self._h)
+
+
+def _lista_function():
+    torch = _torch()
+
+    class LISTA(torch.autograd.Function):
+        """x_{L+1} of unrolled ISTA layers on a lazy matrix, differentiable in
+        the per-layer step a and threshold theta (1-D tensors of length L).
+        The forward pass and the reverse pass are queries on the same handle
+        (2L and 2(L-1) of them), so the gradient is that of one fixed Q."""
+
+        @staticmethod
+        def forward(ctx, a, theta, A, x1, y):
+            ah = a.detach().float().cpu().tolist()
+            th = theta.detach().float().cpu().tolist()
+            X, U, V = A.lista_forward(ah, th, x1, y)
+            ctx.A, ctx.ah, ctx.th, ctx.U, ctx.V = A, ah, th, U, V
+            ctx.like = (a, theta)
+            return X[-1].clone()
+
+        @staticmethod
+        def backward(ctx, gx):
+            ga, gt, _ = ctx.A.lista_backward(ctx.ah, ctx.th, ctx.U, ctx.V,
+                                             gx.contiguous())
+            a, theta = ctx.like
+            return (ga.to(device=a.device, dtype=a.dtype),
+                    gt.to(device=theta.device, dtype=theta.dtype), None, None,
+                    None)
+
+    return LISTA
+
+
+def lista(a, theta, A, x1, y):
+    """Differentiable unrolled ISTA on the lazy matrix A (see LISTA)."""
+    global _LISTA
+    if _LISTA is None:
+        _LISTA = _lista_function()
+    return _LISTA.apply(a, theta, A, x1, y)
+
+
+_LISTA = None

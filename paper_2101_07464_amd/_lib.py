@@ -33,7 +33,8 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_counts", "hd_reset", "hd_set_stream", "hd_pivots", "hd_run",
            "hd_profile", "hd_profile_read", "hd_strerror",
            "hd_batch_init", "hd_batch_run", "hd_batch_status",
-           "hd_batch_set_stream", "hd_batch_free"]
+           "hd_batch_set_stream", "hd_batch_free", "hd_lista_forward",
+           "hd_lista_backward"]
 
 
 class HDConfig(ctypes.Structure):
@@ -98,6 +99,11 @@ def load():
         "hd_batch_status": (i32, [vp]),
         "hd_batch_set_stream": (i32, [vp, vp]),
         "hd_batch_free": (i32, [vp]),
+        "hd_lista_forward": (i32, [vp, i32, P(ctypes.c_float),
+                                   P(ctypes.c_float), vp, vp, vp, vp]),
+        "hd_lista_backward": (i32, [vp, i32, P(ctypes.c_float),
+                                    P(ctypes.c_float), vp, vp, vp, vp, vp,
+                                    vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -55,6 +55,8 @@ struct hd_ctx {
   void* ring[3];   // internal trajectory vectors for hd_run
   void* ybuf;
   void* zeros;
+  void* ista[6];   // unrolled-ISTA work vectors (max(m, n) entries each)
+  double* ista_part;
   int t, r, l;
   std::vector<void*> allocs;
   // profiling
@@ -871,6 +873,113 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
     HIPC(hipMemcpyAsync(x_out, xrow(T + 1), vb, hipMemcpyDeviceToDevice,
                         h->stream));
   return HD_OK;
+}
+
+// Work buffers of the unrolled-ISTA entry points, allocated on first use.
+static int ista_buffers(hd_ctx* h) {
+  if (h->ista[0]) return HD_OK;
+  const int64_t len = h->cfg.m > h->cfg.n ? h->cfg.m : h->cfg.n;
+  for (int i = 0; i < 6; ++i) {
+    int rc = dalloc(h, &h->ista[i], (size_t)h->es * (size_t)len);
+    if (rc) return rc;
+  }
+  return dalloc(h, &h->ista_part, sizeof(double) * 2 * 1024);
+}
+
+// Room for `nq` more queries, pq of them Q-queries (Ginibre also needs
+// r <= n and l <= m).
+static int ista_room(const hd_ctx* h, int nq, int pq) {
+  if ((int64_t)h->t + nq > h->cfg.t_max) return HD_ERR_CAPACITY;
+  if (h->cfg.ensemble == HD_GINIBRE &&
+      ((int64_t)h->r + pq > h->cfg.n || (int64_t)h->l + (nq - pq) > h->cfg.m))
+    return HD_ERR_CAPACITY;
+  return HD_OK;
+}
+
+int hd_lista_forward(hd_handle h, int32_t L, const float* a,
+                     const float* theta, const void* yobs, void* X, void* U,
+                     void* V) {
+  if (!h || L < 1 || !a || !theta || !yobs || !X || !U || !V)
+    return HD_ERR_INVALID;
+  int rc = ista_room(h, 2 * L, L);
+  if (rc) return rc;
+  rc = ista_buffers(h);
+  if (rc) return rc;
+  const size_t vn = (size_t)h->es * (size_t)h->cfg.n;
+  void* r = h->ista[0];
+  void* res = h->ista[1];
+  for (int t = 0; t < L; ++t) {
+    const void* xt = (const char*)X + vn * t;
+    // y - Q x_t, fused into the Q-query's epilogue
+    DynFuse f1 = no_dyn();
+    f1.kind = kDynResidual;
+    f1.x = yobs;
+    f1.xnext = res;
+    h->hint = 1;
+    rc = query(h, 0, xt, r, 0, f1);
+    if (rc) break;
+    // u_t = Q'(y - Q x_t); v_t = x_t + a_t u_t; x_{t+1} = soft(v_t, theta_t)
+    DynFuse f2 = no_dyn();
+    f2.kind = kDynLista;
+    f2.a = a[t];
+    f2.b = theta[t];
+    f2.x = xt;
+    f2.xnext = (char*)X + vn * (t + 1);
+    f2.aux = (char*)V + vn * t;
+    h->hint = t + 1 < L ? 0 : -1;
+    rc = query(h, 1, res, (char*)U + vn * t, 0, f2);
+    if (rc) break;
+  }
+  h->hint = -1;
+  return rc;
+}
+
+int hd_lista_backward(hd_handle h, int32_t L, const float* a,
+                      const float* theta, const void* U, const void* V,
+                      const void* g, double* grad_a, double* grad_theta,
+                      void* g_x1) {
+  if (!h || L < 1 || !a || !theta || !U || !V || !g || !grad_a ||
+      !grad_theta)
+    return HD_ERR_INVALID;
+  const int pairs = L - 1 + (g_x1 ? 1 : 0);
+  int rc = ista_room(h, 2 * pairs, pairs);
+  if (rc) return rc;
+  rc = ista_buffers(h);
+  if (rc) return rc;
+  const int64_t n = h->cfg.n;
+  const size_t vn = (size_t)h->es * (size_t)n;
+  void* gbar = h->ista[2];
+  void* q = h->ista[3];
+  void* w = h->ista[4];
+  void* gnext = h->ista[5];
+  const void* gcur = g;
+  for (int t = L - 1; t >= 0; --t) {
+    ListaAdjArgs k;
+    k.g = gcur;
+    k.v = (const char*)V + vn * t;
+    k.u = (const char*)U + vn * t;
+    k.gbar = gbar;
+    k.theta = theta[t];
+    k.n = n;
+    k.part = h->ista_part;
+    LCHK(launch_lista_adj(h->f64, k, grad_a + t, grad_theta + t, h->stream));
+    if (t == 0 && !g_x1) break;
+    // dL/dx_t = gbar - a_t Q'Q gbar: two more queries on the same Q
+    h->hint = 1;
+    rc = query(h, 0, gbar, q, 0, no_dyn());
+    if (rc) break;
+    DynFuse f = no_dyn();
+    f.kind = kDynAxpy;
+    f.a = a[t];
+    f.x = gbar;
+    f.xnext = t == 0 ? g_x1 : gnext;
+    h->hint = t > 0 && (t > 1 || g_x1) ? 0 : -1;
+    rc = query(h, 1, q, w, 0, f);
+    if (rc) break;
+    gcur = gnext;
+  }
+  h->hint = -1;
+  return rc;
 }
 
 int hd_profile(hd_handle h, int32_t enable) {

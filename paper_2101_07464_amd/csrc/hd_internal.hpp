@@ -92,8 +92,18 @@ struct GinSmallArgs {
   int* flag;
 };
 
-// Element-wise map f_t fused into the random-side epilogue (kind 0: none).
-enum DynKind { kDynNone = 0, kDynTanh = 1, kDynSoftHist = 2, kDynNormalize = 3 };
+// Element-wise map fused into the random-side epilogue (kind 0: none):
+// the built-in f_t, or a piece of an unrolled ISTA layer (eq. (ista) with a
+// learned step a and threshold b per layer).
+enum DynKind {
+  kDynNone = 0,
+  kDynTanh = 1,      // xnext = tanh(a y) + b x
+  kDynSoftHist = 2,  // xnext = soft(y, a) + b xprev
+  kDynNormalize = 3, // (unfused; see k_dyn)
+  kDynResidual = 4,  // xnext = x - y                (x: the observation)
+  kDynLista = 5,     // aux = v = x + a y; xnext = soft(v, b)
+  kDynAxpy = 6       // xnext = x - a y
+};
 
 struct DynFuse {
   int kind;
@@ -101,6 +111,7 @@ struct DynFuse {
   const void* x;      // x_t
   const void* xprev;  // x_{t-1}
   void* xnext;        // x_{t+1}
+  void* aux;          // second output (kDynLista)
 };
 
 // Partial dots of panel columns with a right-hand side b (from memory, or the
@@ -289,6 +300,24 @@ int launch_small_data(const SmallDataArgs& a, hipStream_t s);
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);
 int launch_gin_small(int f64, const GinSmallArgs& a, hipStream_t s);
 int launch_dyn(int f64, const DynArgs& a, hipStream_t s);
+
+// Reverse pass of one unrolled ISTA layer (element-wise part): gbar and the
+// two parameter-gradient sums (see k_lista_adj).
+struct ListaAdjArgs {
+  const void* g;  // dL/dx_{t+1}
+  const void* v;  // v_t
+  const void* u;  // u_t
+  void* gbar;     // out
+  double theta;
+  int64_t n;
+  double* part;   // 2 * lista_blocks(n) doubles
+};
+inline int lista_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+int launch_lista_adj(int f64, const ListaAdjArgs& a, double* ga, double* gt,
+                     hipStream_t s);
 int launch_fill(double* p, double v, int64_t count, hipStream_t s);
 
 }  // namespace hd

@@ -444,12 +444,32 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
     data_tcol<T>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot, lds);
 }
 
-// Element-wise map f_t on one row (y already rounded to storage).
-__device__ __forceinline__ double dyn_row(const DynFuse& d, double yi,
-                                          double xi, double xpi) {
-  if (d.kind == kDynTanh) return tanh(d.a * yi) + d.b * xi;
-  const double m = fabs(yi) - d.a;
-  return (m > 0.0 ? copysign(m, yi) : 0.0) + d.b * xpi;
+__device__ __forceinline__ double soft(double v, double th) {
+  const double m = fabs(v) - th;
+  return m > 0.0 ? copysign(m, v) : 0.0;
+}
+
+// Element-wise epilogue on row i of a query's output y (already rounded to
+// storage): the built-in f_t, or one piece of an unrolled ISTA layer.
+template <typename T>
+__device__ __forceinline__ void dyn_store(const DynFuse& d, int64_t i,
+                                          double y) {
+  const double x = (double)((const T*)d.x)[i];
+  double out;
+  if (d.kind == kDynTanh) {
+    out = tanh(d.a * y) + d.b * x;
+  } else if (d.kind == kDynSoftHist) {
+    out = soft(y, d.a) + d.b * (double)((const T*)d.xprev)[i];
+  } else if (d.kind == kDynResidual) {
+    out = x - y;  // observation minus Q x_t
+  } else if (d.kind == kDynLista) {
+    const T v = (T)(x + d.a * y);  // v_t = x_t + a_t Q'(.)
+    ((T*)d.aux)[i] = v;
+    out = soft((double)v, d.b);
+  } else {  // kDynAxpy
+    out = x - d.a * y;
+  }
+  ((T*)d.xnext)[i] = (T)out;
 }
 
 // ------------------------------------------------------------------ TDOT --
@@ -569,13 +589,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
         const T ys = (T)(sg * w + vz[c]);
         ((T*)a.y)[i] = ys;
         ysq += (double)ys * (double)ys;
-        if (a.dyn.kind) {
-          const double xi = (double)((const T*)a.dyn.x)[i];
-          const double xpi = a.dyn.kind == kDynSoftHist
-                                 ? (double)((const T*)a.dyn.xprev)[i]
-                                 : 0.0;
-          ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
-        }
+        if (a.dyn.kind) dyn_store<T>(a.dyn, i, (double)ys);
         if (i > k) {
           const T gs = (T)gcur[q];
           V[(int64_t)k * a.ld + i] = gs;
@@ -661,13 +675,7 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
     const double hv = (i < k) ? a.h[i] : 0.0;
     const T ys = (T)(sigma * (u1[c] + sg * (hv + nu * gi)));
     ((T*)a.y)[i] = ys;
-    if (a.dyn.kind) {
-      const double xi = (double)((const T*)a.dyn.x)[i];
-      const double xpi = a.dyn.kind == kDynSoftHist
-                             ? (double)((const T*)a.dyn.xprev)[i]
-                             : 0.0;
-      ((T*)a.dyn.xnext)[i] = (T)dyn_row(a.dyn, (double)ys, xi, xpi);
-    }
+    if (a.dyn.kind) dyn_store<T>(a.dyn, i, (double)ys);
   }
 }
 
@@ -686,6 +694,54 @@ __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
 template <typename T, int CPT>
 __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
   gin_pass_body<T, CPT>(a, blockIdx.x);
+}
+
+// --------------------------------------------------- ISTA layer adjoint --
+
+// One layer of the reverse pass: gbar = g * [|v| > theta] and the per-block
+// sums of gbar * u (for dL/da) and of -g * sign(v) * [|v| > theta] (for
+// dL/dtheta) into part[2 b], part[2 b + 1].
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_lista_adj(ListaAdjArgs a) {
+  __shared__ double scr[kWaves];
+  const T* g = (const T*)a.g;
+  const T* v = (const T*)a.v;
+  const T* u = (const T*)a.u;
+  T* gbar = (T*)a.gbar;
+  double sa = 0.0, st = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * kWG) {
+    const double vi = (double)v[i], gi = (double)g[i];
+    const bool on = fabs(vi) > a.theta;
+    const double gb = on ? gi : 0.0;
+    gbar[i] = (T)gb;
+    sa += gb * (double)u[i];
+    if (on) st -= vi > 0.0 ? gi : -gi;
+  }
+  sa = block_sum(sa, scr);
+  st = block_sum(st, scr);
+  if (threadIdx.x == 0) {
+    a.part[2 * blockIdx.x] = sa;
+    a.part[2 * blockIdx.x + 1] = st;
+  }
+}
+
+// Fixed-order sum of the per-block pairs into grad_a[t], grad_theta[t].
+__global__ __launch_bounds__(kWG) void k_lista_sum(const double* part,
+                                                   int nblk, double* ga,
+                                                   double* gt) {
+  __shared__ double scr[kWaves];
+  double sa = 0.0, st = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kWG) {
+    sa += part[2 * b];
+    st += part[2 * b + 1];
+  }
+  sa = block_sum(sa, scr);
+  st = block_sum(st, scr);
+  if (threadIdx.x == 0) {
+    *ga = sa;
+    *gt = st;
+  }
 }
 
 // ------------------------------------------------------- batched kernels --
@@ -1069,6 +1125,22 @@ int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
 int launch_copy_jobs(const CopyJob* jobs, int count, hipStream_t s) {
   if (count <= 0) return 0;
   hipLaunchKernelGGL(k_copy_jobs, dim3(count), dim3(kWG), 0, s, jobs);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_lista_adj(int f64, const ListaAdjArgs& a, double* ga, double* gt,
+                     hipStream_t s) {
+  const int nblk = lista_blocks(a.n);
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_lista_adj<double>), dim3(nblk),
+                       dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_lista_adj<float>), dim3(nblk),
+                       dim3(kWG), 0, s, a);
+  HD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_lista_sum, dim3(1), dim3(kWG), 0, s, a.part, nblk, ga,
+                     gt);
   HD_CHECK_LAUNCH();
   return 0;
 }
