@@ -23,6 +23,12 @@ Workloads (--workload):
       FP32, all trials in one batch (hd_batch_run); a step runs every trial
       to completion.  Also times the same kind of trials one handle at a time
       (a sample of them) for the batched-vs-plain comparison.
+  c5  Differentiated unrolled ISTA: Gaussian Q (n = 262144, m = 131072,
+      N(0, 1/m) entries), y = Q x* + 0.01 noise, x* Bernoulli(0.1)-Gaussian
+      (sd 2), 50 layers with FP32 (a_t, theta_t) = (0.3, 0.6), loss
+      ||x_51 - x*||^2; FP32 storage.  A step is --c5-trials trials, each a
+      fresh Q: forward pass (101 queries) and reverse pass (98 queries);
+      also timed forward-only.
 """
 import argparse
 import json
@@ -164,13 +170,78 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+C5 = dict(name="ista50_ginibre_n262144_m131072_fp32", n=262144, m=131072,
+          L=50, a=0.3, theta=0.6)
+
+
+def main_adjoint(args):
+    import torch
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import inputs
+    dev = "cuda:0"
+    n, m, L = C5["n"], C5["m"], C5["L"]
+    K = args.c5_trials
+    sig = 1.0 / np.sqrt(m)
+    xs = [torch.from_numpy(inputs.sparse_target(n, 0.1, 2.0, seed=0,
+                                                trial=b)).to(dev, torch.float32)
+          for b in range(K)]
+    nz = [torch.from_numpy(inputs.noise(m, 0.01, seed=0, trial=b)).to(
+        dev, torch.float32) for b in range(K)]
+    a = [C5["a"]] * L
+    th = [C5["theta"]] * L
+    tq = 1 + 2 * L + 2 * (L - 1)
+    A = hd.LazyMatrix(hd.GINIBRE, n, m=m, t_max=tq, seed=0, sigma=sig,
+                      device=dev)
+    z = torch.zeros(n, device=dev)
+
+    def trial(b, backward):
+        A.reset(0, b)
+        y = A.mv(xs[b]) + nz[b]
+        X, U, V = A.lista_forward(a, th, z, y)
+        if backward:
+            A.lista_backward(a, th, U, V, 2.0 * (X[-1] - xs[b]))
+
+    def timed(backward):
+        for i in range(args.warmup):
+            trial(i % K, backward)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for b in range(K):
+                trial(b, backward)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_fb = timed(True)
+    t_f = timed(False)
+    if A.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    W_fb = K * nominal_work(n, tq)
+    W_f = K * nominal_work(n, 1 + 2 * L)
+    out = {
+        "metric": METRIC, "value": W_fb / t_fb, "unit": "elem-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_fb * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": C5["name"], "trials_per_step": K,
+                   "queries_per_trial": tq, "elem_updates_per_step": W_fb},
+        "forward_only": {"value": W_f / t_f, "unit": "elem-updates/s",
+                         "ms_per_step": t_f * 1e3,
+                         "queries_per_trial": 1 + 2 * L},
+        "adjoint_time_over_forward": t_fb / t_f,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2",
-                    choices=sorted(list(WORKLOADS) + ["c3"]))
+                    choices=sorted(list(WORKLOADS) + ["c3", "c5"]))
+    ap.add_argument("--c5-trials", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -180,6 +251,9 @@ def main():
 
     if args.workload == "c3":
         main_batch(args)
+        return
+    if args.workload == "c5":
+        main_adjoint(args)
         return
 
     import torch
