@@ -144,24 +144,17 @@ hipEvent_t prof_event(hd_ctx* h) {
   return h->pool[h->pool_used++];
 }
 
+// Timing of one panel launch: when profiling, a pair of events that the
+// dispatch itself records at the kernel's start and end.
 struct ProfScope {
-  hd_ctx* h;
-  int kind;
-  double bytes;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(hd_ctx* h_, int kind_, double bytes_)
-      : h(h_), kind(kind_), bytes(bytes_) {
-    if (h->prof) {
-      a = prof_event(h);
-      b = prof_event(h);
-      if (a && b) (void)hipEventRecord(a, h->stream);
-    }
-  }
-  ~ProfScope() {
-    if (h->prof && a && b) {
-      (void)hipEventRecord(b, h->stream);
-      h->recs.push_back(ProfRec{kind, a, b, bytes});
-    }
+  LaunchEvents ev;
+  ProfScope(hd_ctx* h, int kind, double bytes) {
+    if (!h->prof) return;
+    hipEvent_t a = prof_event(h), b = prof_event(h);
+    if (!a || !b) return;
+    ev.start = a;
+    ev.stop = b;
+    h->recs.push_back(ProfRec{kind, a, b, bytes});
   }
 };
 
@@ -268,7 +261,7 @@ int do_tdot(hd_ctx* h, int side, const TdotArgs& a, const After& af,
             double bytes) {
   {
     ProfScope ps(h, 0, bytes);
-    LCHK(launch_tdot(h->f64, h->sh[side], a, h->stream));
+    LCHK(launch_tdot(h->f64, h->sh[side], a, h->stream, ps.ev));
   }
   return run_after(h, side, af);
 }
@@ -277,7 +270,7 @@ int do_pass(hd_ctx* h, int side, int mode, const PassArgs& a,
             const After& af, int kind, double bytes) {
   {
     ProfScope ps(h, kind, bytes);
-    LCHK(launch_pass(h->f64, h->sh[side], mode, a, h->stream));
+    LCHK(launch_pass(h->f64, h->sh[side], mode, a, h->stream, ps.ev));
   }
   return run_after(h, side, af);
 }
@@ -460,7 +453,8 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
       ProfScope ps(h, 2,
                    es * ((double)h->ld[gs] * k + n + (n - k) +
                          (dyn.kind ? 2.0 * n : 0.0)));
-      LCHK(launch_pass(h->f64, h->sh[gs], kPassRandHaar, a, h->stream));
+      LCHK(launch_pass(h->f64, h->sh[gs], kPassRandHaar, a, h->stream,
+                       ps.ev));
     }
     defer_after(h, gs, want);
     if (want_ysq) {
@@ -569,7 +563,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
       ProfScope ps(h, 2,
                    es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
                          (dyn.kind ? 2.0 * nG : 0.0)));
-      LCHK(launch_gin_pass(h->f64, h->sh[gs], a, h->stream));
+      LCHK(launch_gin_pass(h->f64, h->sh[gs], a, h->stream, ps.ev));
     }
     defer_after(h, gs, want);
   }

@@ -280,10 +280,18 @@ struct CopyJob {
 };
 int launch_copy_jobs(const CopyJob* jobs, int count, hipStream_t s);
 
-int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s);
+// Optional events recorded by the dispatch itself at the kernel's start and
+// end (hipExtLaunchKernelGGL), for timing without extra packets around it.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s,
+                LaunchEvents ev = LaunchEvents());
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
-                hipStream_t s);
-int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s);
+                hipStream_t s, LaunchEvents ev = LaunchEvents());
+int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s,
+                    LaunchEvents ev = LaunchEvents());
 // Fixed-order sums of the partial rows of one pass: out[slot] = sum over
 // rows w < nwg of P[w * pstride + slot], for the slots in rg.
 struct ReduceJob {

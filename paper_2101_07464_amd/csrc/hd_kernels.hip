@@ -26,6 +26,7 @@
 // are bitwise reproducible run to run.  GEMV-N rows are summed over the four
 // waves through LDS in fixed order.  Small one-workgroup FP64 kernels update
 // the WY factor T and the reflector scalars.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "hd_device.hpp"
@@ -974,55 +975,85 @@ __global__ __launch_bounds__(kWG) void k_fill(double* p, double v,
       return -1;                                                        \
   } while (0)
 
+// Launch of a panel kernel, with the timing events inside the dispatch when
+// given.
+template <typename... KArgs, typename... Args>
+static void panel_launch(void (*k)(KArgs...), int nwg, hipStream_t s,
+                         LaunchEvents ev, Args... args) {
+  if (ev.start)
+    hipExtLaunchKernelGGL(k, dim3(nwg), dim3(kWG), 0, s, ev.start, ev.stop, 0,
+                          args...);
+  else
+    hipLaunchKernelGGL(k, dim3(nwg), dim3(kWG), 0, s, args...);
+}
+
+#define HD_DISPATCH_EV(SH, KERNEL_T, S, EV, ...)                  \
+  do {                                                            \
+    if ((SH).cpt == 1)                                            \
+      panel_launch(KERNEL_T(1), (SH).nwg, S, EV, __VA_ARGS__);    \
+    else if ((SH).cpt == 2)                                       \
+      panel_launch(KERNEL_T(2), (SH).nwg, S, EV, __VA_ARGS__);    \
+    else if ((SH).cpt == 4)                                       \
+      panel_launch(KERNEL_T(4), (SH).nwg, S, EV, __VA_ARGS__);    \
+    else                                                          \
+      return -1;                                                  \
+  } while (0)
+
 template <typename T, bool GEN, bool TWO>
-static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s) {
+static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s,
+                      LaunchEvents ev) {
 #define K_(C) k_tdot<T, C, GEN, TWO>
-  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+  HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 template <typename T>
-static int tdot_t(Shape sh, const TdotArgs& a, hipStream_t s) {
-  if (a.gen) return tdot_shape<T, true, false>(sh, a, s);
-  if (a.b2) return tdot_shape<T, false, true>(sh, a, s);
-  return tdot_shape<T, false, false>(sh, a, s);
+static int tdot_t(Shape sh, const TdotArgs& a, hipStream_t s,
+                  LaunchEvents ev) {
+  if (a.gen) return tdot_shape<T, true, false>(sh, a, s, ev);
+  if (a.b2) return tdot_shape<T, false, true>(sh, a, s, ev);
+  return tdot_shape<T, false, false>(sh, a, s, ev);
 }
 
-int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s) {
-  return f64 ? tdot_t<double>(sh, a, s) : tdot_t<float>(sh, a, s);
+int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s,
+                LaunchEvents ev) {
+  return f64 ? tdot_t<double>(sh, a, s, ev) : tdot_t<float>(sh, a, s, ev);
 }
 
 template <typename T, int MODE>
-static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s) {
+static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s,
+                      LaunchEvents ev) {
 #define K_(C) k_pass<T, C, MODE>
-  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+  HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
 
 int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
-                hipStream_t s) {
+                hipStream_t s, LaunchEvents ev) {
   if (f64)
-    return mode == kPassData ? pass_shape<double, kPassData>(sh, a, s)
-                             : pass_shape<double, kPassRandHaar>(sh, a, s);
-  return mode == kPassData ? pass_shape<float, kPassData>(sh, a, s)
-                           : pass_shape<float, kPassRandHaar>(sh, a, s);
+    return mode == kPassData ? pass_shape<double, kPassData>(sh, a, s, ev)
+                             : pass_shape<double, kPassRandHaar>(sh, a, s, ev);
+  return mode == kPassData ? pass_shape<float, kPassData>(sh, a, s, ev)
+                           : pass_shape<float, kPassRandHaar>(sh, a, s, ev);
 }
 
 template <typename T>
-static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s) {
+static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s,
+                     LaunchEvents ev) {
 #define K_(C) k_gin_pass<T, C>
-  HD_DISPATCH_SHAPE(sh, K_, dim3(sh.nwg), dim3(kWG), 0, s, a);
+  HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
   HD_CHECK_LAUNCH();
   return 0;
 }
 
-int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s) {
-  return f64 ? gin_shape<double>(sh, a, s) : gin_shape<float>(sh, a, s);
+int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s,
+                    LaunchEvents ev) {
+  return f64 ? gin_shape<double>(sh, a, s, ev) : gin_shape<float>(sh, a, s, ev);
 }
 
 int launch_tdot_batch(int f64, int cpt, int nblk, int two, const TrialDev* d,
