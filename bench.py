@@ -51,7 +51,7 @@ KIND_NAMES = {0: "panel TDOT (k_tdot)", 1: "data-side GEMV-N (k_pass)",
 WORKLOADS = {
     "c2": dict(name="ginibre_n65536_T100_alt_soft_fp32", ensemble="ginibre",
                n=65536, T=100, dyn="soft_hist", a=0.1, b=0.3, pattern="alt",
-               f64=False, x1_scale=1.0),
+               f64=False, x1_scale=1.0, dense=True),
     "c1": dict(name="haar_n1000_T20_tanh_fp64", ensemble="haar", n=1000,
                T=20, dyn="tanh", a=1.0, b=0.5, pattern="Q", f64=True,
                x1_scale=None),
@@ -101,6 +101,42 @@ C3 = dict(name="haar_batch4096_n1e3-1e5_T10-200_tanh2_fp32", count=4096,
 
 def nominal_work(n, T):
     return n * T * (T + 1) / 2.0
+
+
+def dense_direct(wl, x1, steps):
+    """The direct method on the same GPU: draw the dense m x n Gaussian
+    matrix (N(0, sigma^2) entries, torch's generator) and run the same T
+    queries and map as plain matrix-vector products, in the workload's
+    storage type.  Per step: the fill plus the T products."""
+    import torch
+    n, T = wl["n"], wl["T"]
+    sig = 1.0 / np.sqrt(n)
+    g = torch.Generator(device=x1.device)
+    g.manual_seed(0)
+    Q = torch.empty((n, n), dtype=x1.dtype, device=x1.device)
+
+    def step():
+        Q.normal_(0.0, sig, generator=g)
+        x, xp = x1, torch.zeros_like(x1)
+        for t in range(T):
+            tr = wl["pattern"] == "alt" and t % 2 == 1
+            y = torch.mv(Q.t(), x) if tr else torch.mv(Q, x)
+            m = torch.clamp(torch.abs(y) - wl["a"], min=0.0)
+            x, xp = torch.sign(y) * m + wl["b"] * xp, x
+        return x
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    del Q
+    torch.cuda.empty_cache()
+    return {"ms_per_step": dt * 1e3,
+            "method": "dense %dx%d Gaussian fill (torch) + %d torch.mv "
+                      "products, same map, same storage type" % (n, n, T)}
 
 
 def cpu_baseline(wl, budget_s=15.0):
@@ -386,6 +422,10 @@ def main():
                      "avg_launch_us": ms * 1e3 / max(launches, 1),
                      "algorithmic_bytes_per_launch": nbytes / max(launches, 1)},
     }
+    if wl.get("dense", False):
+        out["dense_direct"] = dense_direct(wl, x1, args.steps)
+        out["vs_dense_direct"] = (out["dense_direct"]["ms_per_step"] /
+                                  out["ms_per_step"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
