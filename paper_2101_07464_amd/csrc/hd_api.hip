@@ -42,7 +42,15 @@ struct hd_ctx {
   double* partials;
   double* partials2;  // partial rows of the random-side pass
   ReduceJob deferred; // its sums, launched with the next reduction
+  // The next query's TDOT dots, computed by the last random pass (its panel
+  // is the next data side and its epilogue made the next input): valid for
+  // query `step` on side `side` with input `x` and `nslots` dots.
+  struct {
+    int valid, step, side, nslots;
+    const void* x;
+  } wready;
   double* w;       // TDOT results (pstride)
+  double* wc;      // dots of a pending column's T-column pass (pstride)
   double* zD;      // T' w (t_max)
   double* zG;      // random-side coefficients + scratch (3 t_max)
   double* z2;      // Ginibre: second coefficient vector of the random side
@@ -291,12 +299,13 @@ void defer_after(hd_ctx* h, int side, const After& af) {
 // random side); pf_rand: likewise for the random pass; tcol: the data side's
 // new T column is formed now (in the data pass) rather than by a later pass.
 struct Plan {
-  bool pf_data, pf_rand, tcol;
+  bool pf_data, pf_rand, tcol, wnext;
 };
 
 Plan plan_of(const hd_ctx* h, int ds, int step) {
   Plan p;
   const bool room = step + 1 <= h->cfg.t_max;
+  p.wnext = false;
   if (h->hint == kHintNone) {
     p.pf_data = p.pf_rand = p.tcol = false;
   } else if (h->hint < 0) {
@@ -307,6 +316,8 @@ Plan plan_of(const hd_ctx* h, int ds, int step) {
     p.pf_data = room && next_gs == ds;
     p.pf_rand = room && next_gs != ds;
     p.tcol = next_gs == ds;
+    // the next data side is this query's random side
+    p.wnext = room && next_gs == ds;
   }
   return p;
 }
@@ -342,8 +353,8 @@ int resolve_pending(hd_ctx* h, int side) {
   TdotArgs a = tdot_base(h, side);
   a.ncols = kp;
   a.b = panel_col(h, side, kp);
-  After want = after_of(ranges(0, kp), h->w, 1);
-  want.sd = small_data_args(h, side, kp, h->w, 0, nullptr, nullptr);
+  After want = after_of(ranges(0, kp), h->wc, 1);
+  want.sd = small_data_args(h, side, kp, h->wc, 0, nullptr, nullptr);
   return do_tdot(h, side, a, want,
                  (double)h->es * ((double)h->ld[side] * kp + h->dim[side]));
 }
@@ -353,7 +364,21 @@ int resolve_pending(hd_ctx* h, int side) {
 int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
   const int kp = h->pending[ds];
   h->pending[ds] = -1;
+  const int step = h->t + 1;
+  const bool ready = h->wready.valid && h->wready.step == step &&
+                     h->wready.side == ds && h->wready.x == x &&
+                     h->wready.nslots == kD + nb2 && kp <= 0;
+  if (h->wready.valid && !ready) h->deferred = no_job();  // unused dots
+  h->wready.valid = 0;
   if (kD + nb2 == 0) return HD_OK;
+  if (ready) {
+    // the dots are in the deferred partial rows: sum them and take the
+    // z-step, with no TDOT launch
+    After want = after_of(ranges(0, 0), h->w, 1);
+    want.sd = small_data_args(h, ds, -1, nullptr, kD,
+                              kD > 0 ? h->w : nullptr, h->zD);
+    return run_after(h, ds, want);
+  }
   TdotArgs a = tdot_base(h, ds);
   a.ncols = kD;
   a.V2 = nb2 ? h->B[ds] : nullptr;
@@ -445,10 +470,15 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.pf = pl.pf_rand ? 1 : 0;
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
-    const After want =
+    a.wnext = pl.wnext && !pl.pf_rand && dyn.kind && dyn.next_input;
+    After want =
         after_of(ranges(0, pl.pf_rand ? k + 1 : 0, h->extra,
                         (pl.pf_rand || want_ysq) ? kNumExtra : 0),
                  h->P[gs].red, 0);
+    if (a.wnext) {
+      want = after_of(ranges(0, k + 1), h->w, 0);
+      h->wready = {1, step + 1, gs, k + 1, dyn.xnext};
+    }
     {
       ProfScope ps(h, 2,
                    es * ((double)h->ld[gs] * k + n + (n - k) +
@@ -557,8 +587,13 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.partials = h->partials2;
     a.pstride = h->pstride;
     a.extra = h->extra;
-    const After want = after_of(ranges(0, pl.pf_rand ? kG : 0),
-                                h->P[gs].red, 0);
+    a.wnext = pl.wnext && !pl.pf_rand && dyn.kind && dyn.next_input;
+    After want = after_of(ranges(0, pl.pf_rand ? kG : 0), h->P[gs].red, 0);
+    if (a.wnext) {
+      // next query: data side gs with kG reflectors and kD + 1 basis columns
+      want = after_of(ranges(0, kG + kD + 1), h->w, 0);
+      h->wready = {1, step + 1, gs, kG + kD + 1, dyn.xnext};
+    }
     {
       ProfScope ps(h, 2,
                    es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
@@ -675,6 +710,7 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   h->hint = -1;
   h->deferred = no_job();
   ALLOC(h->w, sizeof(double) * h->pstride);
+  ALLOC(h->wc, sizeof(double) * h->pstride);
   ALLOC(h->zD, sizeof(double) * tm);
   ALLOC(h->zG, sizeof(double) * 3 * (size_t)tm);
   ALLOC(h->head, sizeof(double) * tm);
@@ -727,6 +763,7 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial) {
   }
   h->hint = -1;
   h->deferred = no_job();
+  h->wready.valid = 0;
   return HD_OK;
 }
 
@@ -845,6 +882,7 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
       fz.x = xrow(t);
       fz.xprev = xprev;
       fz.xnext = xrow(t + 1);
+      fz.next_input = t < T;
     }
     int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE,
                    fz);
@@ -909,6 +947,7 @@ int hd_lista_forward(hd_handle h, int32_t L, const float* a,
     f1.kind = kDynResidual;
     f1.x = yobs;
     f1.xnext = res;
+    f1.next_input = 1;
     h->hint = 1;
     rc = query(h, 0, xt, r, 0, f1);
     if (rc) break;
@@ -920,6 +959,7 @@ int hd_lista_forward(hd_handle h, int32_t L, const float* a,
     f2.x = xt;
     f2.xnext = (char*)X + vn * (t + 1);
     f2.aux = (char*)V + vn * t;
+    f2.next_input = t + 1 < L;
     h->hint = t + 1 < L ? 0 : -1;
     rc = query(h, 1, res, (char*)U + vn * t, 0, f2);
     if (rc) break;

@@ -112,6 +112,7 @@ struct DynFuse {
   const void* xprev;  // x_{t-1}
   void* xnext;        // x_{t+1}
   void* aux;          // second output (kDynLista)
+  int next_input;     // host only: xnext is the next query's input
 };
 
 // Partial dots of panel columns with a right-hand side b (from memory, or the
@@ -164,6 +165,11 @@ struct PassArgs {
   uint32_t step;
   int want_ysq;
   DynFuse dyn;
+  // next query's column dots: when set (and pf is not), the dots of columns
+  // 0..k (this panel, including the new column) with the stored x_{t+1}
+  // rows, into slots 0..k -- the TDOT of the next query when this panel is
+  // its data side
+  int wnext;
   // fused prefetch
   int pf;
   uint32_t pf_step;
@@ -197,6 +203,9 @@ struct GinPassArgs {
   Key key;
   uint32_t step;
   DynFuse dyn;
+  // next query's column dots (as in PassArgs): V columns 0..k-1 into slots
+  // 0..k-1 and B columns 0..nb (including the new one) into slots k..k+nb
+  int wnext;
   int pf;
   uint32_t pf_step;
   int64_t pf_cut;

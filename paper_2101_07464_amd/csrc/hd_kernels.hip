@@ -453,8 +453,8 @@ __device__ __forceinline__ double soft(double v, double th) {
 // Element-wise epilogue on row i of a query's output y (already rounded to
 // storage): the built-in f_t, or one piece of an unrolled ISTA layer.
 template <typename T>
-__device__ __forceinline__ void dyn_store(const DynFuse& d, int64_t i,
-                                          double y) {
+__device__ __forceinline__ double dyn_store(const DynFuse& d, int64_t i,
+                                            double y) {
   const double x = (double)((const T*)d.x)[i];
   double out;
   if (d.kind == kDynTanh) {
@@ -470,7 +470,9 @@ __device__ __forceinline__ void dyn_store(const DynFuse& d, int64_t i,
   } else {  // kDynAxpy
     out = x - d.a * y;
   }
-  ((T*)d.xnext)[i] = (T)out;
+  const T stored = (T)out;
+  ((T*)d.xnext)[i] = stored;
+  return (double)stored;
 }
 
 // ------------------------------------------------------------------ TDOT --
@@ -590,15 +592,26 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
         const T ys = (T)(sg * w + vz[c]);
         ((T*)a.y)[i] = ys;
         ysq += (double)ys * (double)ys;
-        if (a.dyn.kind) dyn_store<T>(a.dyn, i, (double)ys);
+        double xn = 0.0;
+        if (a.dyn.kind) xn = dyn_store<T>(a.dyn, i, (double)ys);
         if (i > k) {
           const T gs = (T)gcur[q];
           V[(int64_t)k * a.ld + i] = gs;
           pfnew += (double)gs * gnext;
         }
+        gcur[q] = xn;  // this thread's own entry, already used
       }
     }
     if (MODE == kPassData) gcur[q] = unew;
+    if (MODE == kPassRandHaar && i >= a.n) gcur[q] = 0.0;
+  }
+  if (MODE == kPassRandHaar && a.wnext) {
+    // the next query's TDOT over this panel (columns 0..k) with x_{t+1}
+    __syncthreads();
+    double xr[CPT][4];
+    lane_rows<CPT>(gcur, xr);
+    sweep<T, CPT, 1, 0>(V, a.ld, k + 1, blk0, xr, xr, true, nullptr, 0.0,
+                        nullptr, 0.0, acc, acc, out, nullptr);
   }
   if (MODE == kPassData && a.cslot >= 0) {
     // dots of the earlier columns with the new one, for its T column (these
@@ -669,14 +682,29 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   for (int c = 0; c < CPT; ++c) {
     const int q = c * kChunkRows + tid;
     const int64_t i = blk0 + q;
-    if (i >= a.n) continue;
-    const double sg = (i < k) ? a.pi[i + 1] : pik;
-    const double gi = gcur[q];
-    B[(int64_t)nb * a.ld + i] = (T)(sg * gi + u0[c]);
-    const double hv = (i < k) ? a.h[i] : 0.0;
-    const T ys = (T)(sigma * (u1[c] + sg * (hv + nu * gi)));
-    ((T*)a.y)[i] = ys;
-    if (a.dyn.kind) dyn_store<T>(a.dyn, i, (double)ys);
+    double xn = 0.0;
+    if (i < a.n) {
+      const double sg = (i < k) ? a.pi[i + 1] : pik;
+      const double gi = gcur[q];
+      B[(int64_t)nb * a.ld + i] = (T)(sg * gi + u0[c]);
+      const double hv = (i < k) ? a.h[i] : 0.0;
+      const T ys = (T)(sigma * (u1[c] + sg * (hv + nu * gi)));
+      ((T*)a.y)[i] = ys;
+      if (a.dyn.kind) xn = dyn_store<T>(a.dyn, i, (double)ys);
+    }
+    gcur[q] = xn;  // this thread's own entry, already used
+  }
+  if (a.wnext) {
+    // the next query's TDOT over this side's panels with x_{t+1}: the
+    // reflector columns 0..k-1 and the basis columns 0..nb (the new one
+    // included; its rows were written above by this workgroup)
+    __syncthreads();
+    double xr[CPT][4];
+    lane_rows<CPT>(gcur, xr);
+    sweep<T, CPT, 1, 0>((const T*)a.V, a.ld, k, blk0, xr, xr, true, nullptr,
+                        0.0, nullptr, 0.0, acc0, acc0, out, nullptr);
+    sweep<T, CPT, 1, 0>((const T*)B, a.ld, nb + 1, blk0, xr, xr, true, nullptr,
+                        0.0, nullptr, 0.0, acc0, acc0, out + k, nullptr);
   }
 }
 
