@@ -49,6 +49,11 @@ struct hd_ctx {
     int valid, step, side, nslots;
     const void* x;
   } wready;
+  // The data pass forms z = T' w itself (its prologue) from h->w, with the
+  // pending T column kp (dots in h->w + slot2) when kp > 0.
+  struct {
+    int use, kp;
+  } zpro;
   double* w;       // TDOT results (pstride)
   double* wc;      // dots of a pending column's T-column pass (pstride)
   double* zD;      // T' w (t_max)
@@ -370,11 +375,18 @@ int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
                      h->wready.nslots == kD + nb2 && kp <= 0;
   if (h->wready.valid && !ready) h->deferred = no_job();  // unused dots
   h->wready.valid = 0;
+  h->zpro.use = 0;
   if (kD + nb2 == 0) return HD_OK;
+  // z-step in the data pass's prologue where its shape allows
+  const bool zp = h->sh[ds].cpt == 1 && kD <= kZproMax;
+  if (zp) {
+    h->zpro.use = 1;
+    h->zpro.kp = ready ? -1 : kp;
+  }
   if (ready) {
-    // the dots are in the deferred partial rows: sum them and take the
-    // z-step, with no TDOT launch
-    After want = after_of(ranges(0, 0), h->w, 1);
+    // the dots are in the deferred partial rows: sum them (and take the
+    // z-step), with no TDOT launch
+    After want = after_of(ranges(0, 0), h->w, zp ? 0 : 1);
     want.sd = small_data_args(h, ds, -1, nullptr, kD,
                               kD > 0 ? h->w : nullptr, h->zD);
     return run_after(h, ds, want);
@@ -386,13 +398,26 @@ int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
   a.b = x;
   a.b2 = kp > 0 ? panel_col(h, ds, kp) : nullptr;
   After want = after_of(ranges(0, kD + nb2, h->slot2, kp > 0 ? kp : 0), h->w,
-                      1);
+                      zp ? 0 : 1);
   want.sd = small_data_args(h, ds, kp, h->w + h->slot2, kD,
                             kD > 0 ? h->w : nullptr, h->zD);
   const double n = (double)h->dim[ds];
   return do_tdot(h, ds, a, want,
                  (double)h->es * ((double)h->ld[ds] * (kD + nb2) + n +
                                   (kp > 0 ? n : 0.0)));
+}
+
+// The data pass's z prologue (see hd_ctx::zpro).
+void set_zpro(hd_ctx* h, int ds, PassArgs& a) {
+  if (!h->zpro.use) return;
+  a.zpro = 1;
+  a.w = h->w;
+  a.c = h->w + h->slot2;
+  a.kp = h->zpro.kp;
+  a.T = h->P[ds].T;
+  a.tau = h->P[ds].tau;
+  a.tmax = h->cfg.t_max;
+  h->zpro.use = 0;
 }
 
 DynFuse no_dyn() {
@@ -434,6 +459,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = k + 1;
     a.cslot = pl.tcol && k > 0 ? h->slot2 : -1;
+    set_zpro(h, ds, a);
     After want = after_of(ranges(0, pl.pf_data ? k + 1 : 0, h->slot2,
                                  a.cslot >= 0 ? k : 0, h->extra, kNumExtra),
                           h->P[ds].red, 2);
@@ -541,6 +567,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.pf_step = (uint32_t)(step + 1);
     a.pf_cut = kD;
     a.cslot = pl.tcol && kD > 0 ? h->slot2 : -1;
+    set_zpro(h, ds, a);
     After want = after_of(ranges(0, pl.pf_data ? kD + 1 : 0, h->slot2,
                                  a.cslot >= 0 ? kD : 0, h->extra, kNumExtra),
                           h->P[ds].red, 3);
@@ -764,6 +791,7 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial) {
   h->hint = -1;
   h->deferred = no_job();
   h->wready.valid = 0;
+  h->zpro.use = 0;
   return HD_OK;
 }
 

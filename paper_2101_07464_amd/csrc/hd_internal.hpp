@@ -152,6 +152,16 @@ struct PassArgs {
   const double* z;   // k coefficients
   const double* pi;  // prefix sign products pi[0..k]
   int64_t n;
+  // data mode, z from a prologue (zpro): every workgroup forms
+  // z = T' w itself (with T column kp from the dots c when kp > 0; block 0
+  // stores that column), instead of reading z
+  int zpro;
+  const double* w;
+  const double* c;
+  int kp;
+  double* T;
+  const double* tau;
+  int tmax;
   // data mode: out = Delta (x - V z)
   const void* x;
   double* head;   // rows < k of the output (FP64)
@@ -294,6 +304,10 @@ int launch_copy_jobs(const CopyJob* jobs, int count, hipStream_t s);
 struct LaunchEvents {
   hipEvent_t start = nullptr, stop = nullptr;
 };
+
+// Largest k for the data pass's z prologue (its LDS holds 2 * kZproMax
+// doubles); only one-chunk shapes use it.
+constexpr int kZproMax = 512;
 
 int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s,
                 LaunchEvents ev = LaunchEvents());

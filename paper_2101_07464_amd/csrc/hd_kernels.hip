@@ -555,7 +555,44 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     }
   if (a.pf) lane_rows<CPT>(gpf, gn);
   double* out = a.partials + (int64_t)blk * a.pstride;
-  sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, a.z, 1.0, nullptr,
+  const double* z = a.z;
+  if constexpr (MODE == kPassData && CPT == 1) {
+    // z = T' w (and T column kp) computed by every workgroup (see zpro)
+    __shared__ double zl[kZproMax], tc[kZproMax];
+    if (a.zpro) {
+      const int kp = a.kp, tm = a.tmax;
+      const double* __restrict__ Tm = a.T;
+      const double* __restrict__ cc = a.c;
+      const double* __restrict__ w = a.w;
+      double* Tw = a.T;
+      const bool first = blk == 0;
+      if (kp > 0) {
+        const double tau = a.tau[kp];
+        wg_sums<1>(
+            kp, [](int j) { return j; }, [kp](int) { return kp; },
+            [=](int l, int j, double& t0, double& t1) {
+              t0 = Tm[j + (int64_t)l * tm] * cc[l];
+              t1 = 0.0;
+            },
+            [=](int j, double r0, double) {
+              tc[j] = -tau * r0;
+              if (first) Tw[j + (int64_t)kp * tm] = -tau * r0;
+            },
+            comb);
+      }
+      wg_sums<1>(
+          k, [](int) { return 0; }, [](int j) { return j + 1; },
+          [=](int i, int j, double& t0, double& t1) {
+            const double tij =
+                (j == kp && i < kp) ? tc[i] : Tm[i + (int64_t)j * tm];
+            t0 = tij * w[i];
+            t1 = 0.0;
+          },
+          [=](int j, double r0, double) { zl[j] = r0; }, comb);
+      z = zl;
+    }
+  }
+  sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0, nullptr,
                       0.0, acc, acc, out, nullptr);
   double vz[CPT];  // -(V z) for this thread's rows
   combine_rows<CPT>(acc, comb, vz);
