@@ -556,6 +556,9 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
   const Plan pl = plan_of(h, ds, step);
   rc = data_tdot(h, ds, x, kD, kG);
   if (rc) return rc;
+  bool spro = false;
+  GinSmallArgs small;
+  std::memset(&small, 0, sizeof(small));
   {
     PassArgs a = pass_base(h, ds);
     a.k = kD;
@@ -585,6 +588,13 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     gsa.D_extra = h->extra;
     gsa.cslot = a.cslot;
     gsa.flag = h->flag;
+    // the reflector step runs as the random pass's prologue where its
+    // shape allows (one chunk per workgroup, l within the LDS arrays)
+    spro = h->sh[gs].cpt == 1 && kG <= kZproMax;
+    if (spro) {
+      small = gsa;
+      want.op = 0;
+    }
     rc = do_pass(h, ds, kPassData, a, want, 1,
                  es * ((double)h->ld[ds] * kD + nD + (nD - kD)));
     if (rc) return rc;
@@ -592,6 +602,8 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
   {
     GinPassArgs a;
     std::memset(&a, 0, sizeof(a));
+    a.spro = spro ? 1 : 0;
+    a.small = small;
     a.V = h->P[gs].V;
     a.ld = h->ld[gs];
     a.k = kG;

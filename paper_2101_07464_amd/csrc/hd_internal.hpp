@@ -216,6 +216,12 @@ struct GinPassArgs {
   // next query's column dots (as in PassArgs): V columns 0..k-1 into slots
   // 0..k-1 and B columns 0..nb (including the new one) into slots k..k+nb
   int wnext;
+  // reflector step in a prologue (spro): every workgroup forms nu and the
+  // coefficients z1, z2 from `small` itself (instead of reading z1, z2 and
+  // scal[0]); workgroup 0 also stores the data reflector's scalars and, when
+  // small.cslot >= 0, the data side's new T column
+  int spro;
+  GinSmallArgs small;
   int pf;
   uint32_t pf_step;
   int64_t pf_cut;

@@ -702,10 +702,66 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
     }
   if (a.pf) lane_rows<CPT>(gpf, gn);
   double* out = a.partials + (int64_t)blk * a.pstride;
+  const double* z1 = a.z1;
+  const double* z2 = a.z2;
+  double nu = 0.0;
+  bool have_nu = false;
+  if constexpr (CPT == 1) {
+    // the reflector step (as in gin_small_body), computed by every workgroup
+    __shared__ double s1l[kZproMax], s2l[kZproMax], z1l[kZproMax],
+        z2l[kZproMax], shr[3];
+    if (a.spro) {
+      const GinSmallArgs& g = a.small;
+      const int kD = g.k, l = g.l, tm = g.tmax;
+      const double ss = g.D.red[g.D_extra + kSlotSS], pk = *g.pivot;
+      if (blk == 0 && tid == 0) {
+        g.scal[0] = data_reflector<T>(g.D, kD, tm, ss, pk, g.flag, &shr[1],
+                                      &shr[2]);
+      }
+      nu = sqrt(ss + pk * pk);  // the same expression as data_reflector's
+      have_nu = true;
+      const double pil = g.G.pi[l];
+      const T* __restrict__ VG = (const T*)g.G.V;
+      const int64_t ldG = g.G.ld;
+      const double* __restrict__ piG = g.G.pi;
+      const double* __restrict__ hh = g.h;
+      const double* __restrict__ gdot = g.G.red;
+      const double nuv = nu;
+      wg_sums<1>(
+          l, [](int j) { return j; }, [l](int) { return l; },
+          [=](int i, int j, double& t0, double& t1) {
+            t0 = (double)VG[(int64_t)j * ldG + i] * piG[i + 1] * hh[i];
+            t1 = 0.0;
+          },
+          [=](int j, double hs, double) {
+            const double v1 = pil * gdot[j];
+            s1l[j] = v1;
+            s2l[j] = hs + nuv * v1;
+          },
+          comb);
+      const double* __restrict__ TG = g.G.T;
+      wg_sums<2>(
+          l, [](int j) { return j; }, [l](int) { return l; },
+          [=](int q, int j, double& t0, double& t1) {
+            const double tjq = TG[j + (int64_t)q * tm];
+            t0 = tjq * s1l[q];
+            t1 = tjq * s2l[q];
+          },
+          [=](int j, double r0, double r1) {
+            z1l[j] = r0;
+            z2l[j] = r1;
+          },
+          comb);
+      z1 = z1l;
+      z2 = z2l;
+      if (blk == 0 && g.cslot >= 0)
+        data_tcol<T>(g.D, kD, tm, shr[1], shr[2], g.D.red + g.cslot, comb);
+    }
+  }
   // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
   // and the prefetch dots
-  sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, a.z1,
-                      1.0, a.z2, 1.0, acc0, acc1, out, nullptr);
+  sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, z1,
+                      1.0, z2, 1.0, acc0, acc1, out, nullptr);
   // explicit basis panel: acc1 += B c
   if (nb > 0)
     sweep<T, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, gn, gn, false, a.c, -1.0,
@@ -713,7 +769,8 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   double u0[CPT], u1[CPT];
   combine_rows<CPT>(acc0, comb, u0);
   combine_rows<CPT>(acc1, comb, u1);
-  const double nu = a.scal[0], sigma = a.scal[1];
+  if (!have_nu) nu = a.scal[0];
+  const double sigma = a.scal[1];
   const double pik = a.pi[k];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
