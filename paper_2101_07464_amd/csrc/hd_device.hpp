@@ -7,7 +7,7 @@
 //    per-lane partials over the wave with CG - 1 + log2(64/CG) exchanges
 //    instead of CG full reductions, on permlane swaps and DPP moves (no LDS);
 //  * panel row loads (four consecutive rows: one 16-byte load for FP32, two
-//    for FP64).
+//    for FP64), optionally non-temporal.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -208,19 +208,36 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[CG]) {
 
 // ---------------------------------------------------------------- loads ---
 
+// NT: non-temporal loads, for panel streams that nothing re-reads (they
+// then do not displace reusable lines from the caches).
+typedef float hd_f4 __attribute__((ext_vector_type(4)));
+typedef double hd_d2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
 __device__ __forceinline__ void load4(const float* __restrict__ p,
                                       double out[4]) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
+  hd_f4 v;
+  if constexpr (NT)
+    v = __builtin_nontemporal_load((const hd_f4*)p);
+  else
+    v = *(const hd_f4*)p;
   out[0] = v.x;
   out[1] = v.y;
   out[2] = v.z;
   out[3] = v.w;
 }
 
+template <bool NT>
 __device__ __forceinline__ void load4(const double* __restrict__ p,
                                       double out[4]) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  hd_d2 a, b;
+  if constexpr (NT) {
+    a = __builtin_nontemporal_load((const hd_d2*)p);
+    b = __builtin_nontemporal_load((const hd_d2*)(p + 2));
+  } else {
+    a = *(const hd_d2*)p;
+    b = *(const hd_d2*)(p + 2);
+  }
   out[0] = a.x;
   out[1] = a.y;
   out[2] = b.x;

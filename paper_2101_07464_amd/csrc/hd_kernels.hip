@@ -119,8 +119,10 @@ __device__ __forceinline__ void combine_rows(const double (&acc)[CPT][4],
 //   GEMV-N (NZ = 0, 1 or 2): acc_q[r] -= zs_q * sum_j V[r, j] * z_q[j] over
 //        this wave's columns (rows are summed over waves afterwards).
 // Every panel row of the workgroup is allocated (ld is a multiple of the
-// workgroup's rows); rows at or beyond n are zero.
-template <typename T, int CPT, int ND, int NZ>
+// workgroup's rows); rows at or beyond n are zero.  NT: non-temporal panel
+// loads (used for multi-chunk workgroups -- panels far beyond the caches --
+// when no second sweep re-reads the rows).
+template <typename T, int CPT, int ND, int NZ, bool NT = false>
 __device__ __forceinline__ void sweep(
     const T* __restrict__ V, int64_t ld, int nc, int64_t blk0,
     const double (&rhs0)[CPT][4], const double (&rhs1)[CPT][4], bool dots,
@@ -151,7 +153,7 @@ __device__ __forceinline__ void sweep(
       for (int jj = 0; jj < kCG; ++jj) {
         const int j = wave + kWaves * min(g0 + jj, ncw - 1);
         double v[4];
-        load4(Vl + (int64_t)j * ld + c * kChunkRows, v);
+        load4<NT>(Vl + (int64_t)j * ld + c * kChunkRows, v);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if constexpr (NZ >= 1) acc0[c][e] -= v[e] * q0[jj];
@@ -503,13 +505,14 @@ __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
   }
   double* out = a.partials + (int64_t)blk * a.pstride;
   double acc[CPT][4];
-  sweep<T, CPT, TWO ? 2 : 1, 0>((const T*)a.V, a.ld, a.ncols, blk0, rhs0, rhs1,
-                                true, nullptr, 0.0, nullptr, 0.0, acc, acc,
-                                out, out + a.slot2);
+  constexpr bool kNT = CPT > 1;
+  sweep<T, CPT, TWO ? 2 : 1, 0, kNT>((const T*)a.V, a.ld, a.ncols, blk0, rhs0,
+                                     rhs1, true, nullptr, 0.0, nullptr, 0.0,
+                                     acc, acc, out, out + a.slot2);
   if (a.ncols2 > 0)
-    sweep<T, CPT, 1, 0>((const T*)a.V2, a.ld, a.ncols2, blk0, rhs0, rhs1, true,
-                        nullptr, 0.0, nullptr, 0.0, acc, acc, out + a.ncols,
-                        nullptr);
+    sweep<T, CPT, 1, 0, kNT>((const T*)a.V2, a.ld, a.ncols2, blk0, rhs0, rhs1,
+                             true, nullptr, 0.0, nullptr, 0.0, acc, acc,
+                             out + a.ncols, nullptr);
   if (a.want_ss) {
     // sum of squares over the workgroup's rows, once per row
     double ss = 0.0;
@@ -592,8 +595,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
       z = zl;
     }
   }
-  sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0, nullptr,
-                      0.0, acc, acc, out, nullptr);
+  // the second sweeps below re-read these rows: keep them cached then
+  const bool reread = (MODE == kPassData && a.cslot >= 0) ||
+                      (MODE == kPassRandHaar && a.wnext);
+  if (CPT > 1 && !reread)
+    sweep<T, CPT, 1, 1, true>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0,
+                              nullptr, 0.0, acc, acc, out, nullptr);
+  else
+    sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0, nullptr,
+                        0.0, acc, acc, out, nullptr);
   double vz[CPT];  // -(V z) for this thread's rows
   combine_rows<CPT>(acc, comb, vz);
 
@@ -760,12 +770,23 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   }
   // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
   // and the prefetch dots
-  sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, z1,
-                      1.0, z2, 1.0, acc0, acc1, out, nullptr);
-  // explicit basis panel: acc1 += B c
-  if (nb > 0)
-    sweep<T, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, gn, gn, false, a.c, -1.0,
-                        nullptr, 0.0, acc1, acc1, nullptr, nullptr);
+  if (CPT > 1 && !a.wnext) {
+    sweep<T, CPT, 1, 2, true>((const T*)a.V, a.ld, k, blk0, gn, gn,
+                              a.pf != 0, z1, 1.0, z2, 1.0, acc0, acc1, out,
+                              nullptr);
+    // explicit basis panel: acc1 += B c
+    if (nb > 0)
+      sweep<T, CPT, 0, 1, true>((const T*)B, a.ld, nb, blk0, gn, gn, false,
+                                a.c, -1.0, nullptr, 0.0, acc1, acc1, nullptr,
+                                nullptr);
+  } else {
+    sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, z1,
+                        1.0, z2, 1.0, acc0, acc1, out, nullptr);
+    // explicit basis panel: acc1 += B c
+    if (nb > 0)
+      sweep<T, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, gn, gn, false, a.c,
+                          -1.0, nullptr, 0.0, acc1, acc1, nullptr, nullptr);
+  }
   double u0[CPT], u1[CPT];
   combine_rows<CPT>(acc0, comb, u0);
   combine_rows<CPT>(acc1, comb, u1);
