@@ -62,9 +62,9 @@ WORKLOADS = {
                x1_scale=None),
 }
 
-KERNEL_OF_KIND = {(0, "ginibre"): "k_tdot", (1, "ginibre"): "k_pass",
+KERNEL_OF_KIND = {(0, "ginibre"): "k_tdot", (1, "ginibre"): "k_pass<data>",
                   (2, "ginibre"): "k_gin_pass", (0, "haar"): "k_tdot",
-                  (1, "haar"): "k_pass", (2, "haar"): "k_pass"}
+                  (1, "haar"): "k_pass<data>", (2, "haar"): "k_pass<random>"}
 
 
 def kernel_sources_sha256():
