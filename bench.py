@@ -247,6 +247,22 @@ C5 = dict(name="ista50_ginibre_n262144_m131072_fp32", n=262144, m=131072,
           L=50, a=0.3, theta=0.6)
 
 
+def tune_shapes(args, hd, ens, lengths, dtype, k):
+    """Launch shapes for the panels: measured by the library's autotuner
+    (default) or the built-in rule.  Runs before any timed work."""
+    lengths = sorted(set(int(v) for v in lengths))
+    out = {"source": "rule"}
+    if not args.no_autotune:
+        rep = hd.autotune(ens, lengths, dtype, k=k)
+        out = {"source": "autotune", "tuner_trajectory_queries": k,
+               "tuner_us": {str(n): {str(c): round(us, 1)
+                                     for c, us in t.items()}
+                            for n, (_, t) in rep.items()}}
+    out["chunks_per_workgroup"] = {str(n): hd.shape_rule(ens, n, dtype)
+                                   for n in lengths}
+    return out
+
+
 def main_adjoint(args):
     import torch
     import paper_2101_07464_amd as hd
@@ -263,6 +279,7 @@ def main_adjoint(args):
     a = [C5["a"]] * L
     th = [C5["theta"]] * L
     tq = 1 + 2 * L + 2 * (L - 1)
+    shape = tune_shapes(args, hd, hd.GINIBRE, [n, m], torch.float32, 32)
     A = hd.LazyMatrix(hd.GINIBRE, n, m=m, t_max=tq, seed=0, sigma=sig,
                       device=dev)
     z = torch.zeros(n, device=dev)
@@ -298,7 +315,8 @@ def main_adjoint(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": C5["name"], "trials_per_step": K,
-                   "queries_per_trial": tq, "elem_updates_per_step": W_fb},
+                   "queries_per_trial": tq, "elem_updates_per_step": W_fb,
+                   "launch_shape": shape},
         "forward_only": {"value": W_f / t_f, "unit": "elem-updates/s",
                          "ms_per_step": t_f * 1e3,
                          "queries_per_trial": 1 + 2 * L},
@@ -334,6 +352,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in launch-shape rule instead of "
+                         "timing the candidate shapes first")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -362,6 +383,7 @@ def main():
     sig = 1.0 / np.sqrt(n) if ens == hd.GINIBRE else 1.0
     x1 = torch.from_numpy(inputs.x1_normal(n, seed=0, scale=wl["x1_scale"]))
     x1 = x1.to(dev, dtype)
+    shape = tune_shapes(args, hd, ens, [n], dtype, min(T, 32))
     A = hd.LazyMatrix(ens, n, t_max=T, seed=0, sigma=sig, dtype=dtype,
                       device=dev)
 
@@ -414,7 +436,7 @@ def main():
                    "precision": ("FP64 panels and vectors" if wl["f64"] else
                                  "FP32 panels and vectors, FP64 accumulation,"
                                  " norms, signs and T"),
-                   "elem_updates_per_step": W},
+                   "elem_updates_per_step": W, "launch_shape": shape},
         "roofline": {"bound": "hbm", "kernel": KIND_NAMES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -162,6 +162,31 @@ int hd_lista_backward(hd_handle h, int32_t L, const float* a,
                       const void* g, double* grad_a, double* grad_theta,
                       void* g_x1);
 
+/* ------------------------------------------------------------------------
+ * Launch-shape autotuner.  The panel kernels' workgroups cover 1, 2 or 4
+ * chunks of 256 rows; the built-in rule uses 1 below 256K rows, 2 below
+ * 512K, 4 from there on.  hd_autotune times on the device, for every panel length in
+ * `lengths`, a whole trajectory of k queries on a scratch handle of that
+ * size (x_{t+1} = tanh(y_t) + 0.5 x_t; Haar: M_t = Q; Gaussian: sigma^2 =
+ * 1/n, Q and Q' alternating) under each candidate shape, and installs the
+ * fastest, process-wide, for the ensemble and storage type (replacing its
+ * earlier entries).  A handle created afterwards uses, per panel, the entry
+ * whose length is nearest its own in ratio, if within a factor of 2, and
+ * the built-in rule otherwise.  report: NULL or 3 * count doubles receiving
+ * the mean microseconds per trajectory under 1, 2 and 4 chunks.  Not
+ * thread-safe with concurrent hd_init.  The environment variable HD_CPT
+ * (1, 2 or 4), when set, overrides tuned and built-in shapes.
+ * Errors: HD_ERR_INVALID (ensemble, storage, count < 1, k < 2, a length
+ * below k or above 2^31), HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
+                int32_t count, int32_t k, void* stream, double* report);
+
+/* The chunks per workgroup a handle's panel of length n would use now. */
+int hd_shape_rule(int32_t ensemble, int32_t storage, int64_t n, int32_t* cpt);
+
+/* Forget every tuned shape (back to the built-in rule). */
+int hd_autotune_clear(void);
+
 /* Timing of the panel kernels with HIP events on the handle's stream.
  * hd_profile(h, 1) starts recording (clears previous records), 0 stops. */
 int hd_profile(hd_handle h, int32_t enable);

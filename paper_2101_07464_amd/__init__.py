@@ -329,3 +329,52 @@ def lista(a, theta, A, x1, y):
 
 
 _LISTA = None
+
+
+def _storage(dtype):
+    torch = _torch()
+    if dtype not in (torch.float32, torch.float64):
+        raise TypeError("dtype must be float32 or float64")
+    return HD_F64 if dtype == torch.float64 else HD_F32
+
+
+def autotune(ensemble, lengths, dtype=None, k=8, device="cuda:0"):
+    """Pick the panel kernels' launch shape per panel length on the device.
+
+    For every length it times a whole trajectory of ``k`` queries of the
+    ensemble (GINIBRE or HAAR) under each shape (workgroups of 1, 2 or 4
+    chunks of 256 rows) and installs the fastest one process-wide for
+    handles of that ensemble and storage type created afterwards.
+    Returns {length: (chosen chunks, {chunks: microseconds})}.
+    """
+    torch = _torch()
+    dtype = torch.float32 if dtype is None else dtype
+    st = _storage(dtype)
+    lengths = [int(v) for v in lengths]
+    arr = (ctypes.c_int64 * len(lengths))(*lengths)
+    rep = (ctypes.c_double * (3 * len(lengths)))()
+    device = torch.device(device)
+    with torch.cuda.device(device):
+        _lib.check(_lib.load().hd_autotune(ensemble, st, arr, len(lengths),
+                                           int(k), _stream_ptr(device), rep),
+                   "hd_autotune")
+    out = {}
+    for i, n in enumerate(lengths):
+        out[n] = (shape_rule(ensemble, n, dtype),
+                  {c: rep[3 * i + j] for j, c in enumerate((1, 2, 4))})
+    return out
+
+
+def shape_rule(ensemble, n, dtype=None):
+    """Chunks per workgroup a handle's panel of length n would use now."""
+    torch = _torch()
+    dtype = torch.float32 if dtype is None else dtype
+    cpt = ctypes.c_int32()
+    _lib.check(_lib.load().hd_shape_rule(ensemble, _storage(dtype), int(n),
+                                         ctypes.byref(cpt)), "hd_shape_rule")
+    return cpt.value
+
+
+def autotune_clear():
+    """Drop every tuned shape (back to the built-in rule)."""
+    _lib.check(_lib.load().hd_autotune_clear(), "hd_autotune_clear")

@@ -34,7 +34,8 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_profile", "hd_profile_read", "hd_strerror",
            "hd_batch_init", "hd_batch_run", "hd_batch_status",
            "hd_batch_set_stream", "hd_batch_free", "hd_lista_forward",
-           "hd_lista_backward"]
+           "hd_lista_backward", "hd_autotune", "hd_shape_rule",
+           "hd_autotune_clear"]
 
 
 class HDConfig(ctypes.Structure):
@@ -104,6 +105,9 @@ def load():
         "hd_lista_backward": (i32, [vp, i32, P(ctypes.c_float),
                                     P(ctypes.c_float), vp, vp, vp, vp, vp,
                                     vp]),
+        "hd_autotune": (i32, [i32, i32, P(i64), i32, i32, vp, P(dbl)]),
+        "hd_shape_rule": (i32, [i32, i32, i64, P(i32)]),
+        "hd_autotune_clear": (i32, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

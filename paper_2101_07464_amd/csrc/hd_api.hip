@@ -3,6 +3,7 @@
 // hd_kernels.hip; this file only orders launches on the handle's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -110,17 +111,47 @@ int env_int(const char* name, int dflt) {
 }
 
 
-// Workgroups cover 256 * cpt rows: one chunk up to 512K rows (at least 256
-// workgroups from n = 65536 on, one per compute unit), two up to 2M, four
-// beyond.  HD_CPT overrides (tuning).
-Shape pick_shape(int64_t dim, int64_t ld) {
+// Workgroups cover 256 * cpt rows.  Built-in rule, from tuner sweeps of
+// both ensembles and storage types (16- and 64-query trajectories): one
+// chunk below 256K rows, two below 512K, four from there on.  hd_autotune installs measured shapes per
+// ensemble and storage type: (panel length, cpt), sorted by length.  A
+// panel takes the entry whose length is nearest its own in ratio, if that
+// ratio is at most 2.  HD_CPT overrides both.
+std::vector<std::pair<int64_t, int>> g_tuned[2][2];
+
+int tuned_cpt(int ens, int f64, int64_t dim) {
+  int cpt = 0;
+  double best = 2.0;
+  for (const auto& e : g_tuned[ens == HD_HAAR ? 1 : 0][f64 ? 1 : 0]) {
+    const double r = e.first > dim ? (double)e.first / (double)dim
+                                   : (double)dim / (double)e.first;
+    if (r <= best) {
+      best = r;
+      cpt = e.second;
+    }
+  }
+  return cpt;
+}
+
+Shape shape_of(int64_t ld, int cpt) {
   Shape sh;
-  sh.cpt = dim <= ((int64_t)1 << 19) ? 1 : (dim <= ((int64_t)1 << 21) ? 2 : 4);
-  const int cpt = env_int("HD_CPT", 0);
-  if (cpt == 1 || cpt == 2 || cpt == 4) sh.cpt = cpt;
-  const int64_t rows = (int64_t)256 * sh.cpt;
-  sh.nwg = (int)(ld / rows);
+  sh.cpt = cpt;
+  sh.nwg = (int)(ld / ((int64_t)256 * cpt));
   return sh;
+}
+
+// Set only inside hd_autotune: sizes its scratch handle for the one-chunk
+// shape (the most workgroups, hence the largest partial-sum buffers).
+int g_force_cpt = 0;
+
+Shape pick_shape(int ens, int f64, int64_t dim, int64_t ld) {
+  if (g_force_cpt) return shape_of(ld, g_force_cpt);
+  int c = dim < ((int64_t)1 << 18) ? 1 : (dim < ((int64_t)1 << 19) ? 2 : 4);
+  const int t = tuned_cpt(ens, f64, dim);
+  if (t) c = t;
+  const int e = env_int("HD_CPT", 0);
+  if (e == 1 || e == 2 || e == 4) c = e;
+  return shape_of(ld, c);
 }
 
 template <typename P>
@@ -377,8 +408,9 @@ int data_tdot(hd_ctx* h, int ds, const void* x, int kD, int nb2) {
   h->wready.valid = 0;
   h->zpro.use = 0;
   if (kD + nb2 == 0) return HD_OK;
-  // z-step in the data pass's prologue where its shape allows
-  const bool zp = h->sh[ds].cpt == 1 && kD <= kZproMax;
+  // z-step in the data pass's prologue where its shape allows (at most
+  // two chunks per workgroup; k within the LDS arrays)
+  const bool zp = h->sh[ds].cpt <= 2 && kD <= kZproMax;
   if (zp) {
     h->zpro.use = 1;
     h->zpro.kp = ready ? -1 : kp;
@@ -589,8 +621,9 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     gsa.cslot = a.cslot;
     gsa.flag = h->flag;
     // the reflector step runs as the random pass's prologue where its
-    // shape allows (one chunk per workgroup, l within the LDS arrays)
-    spro = h->sh[gs].cpt == 1 && kG <= kZproMax;
+    // shape allows (at most two chunks per workgroup, l within the LDS
+    // arrays)
+    spro = h->sh[gs].cpt <= 2 && kG <= kZproMax;
     if (spro) {
       small = gsa;
       want.op = 0;
@@ -717,7 +750,7 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   int maxwg = 1;
   for (int s = 0; s < 2; ++s) {
     h->ld[s] = round_up(dims[s], kChunk);
-    h->sh[s] = pick_shape(dims[s], h->ld[s]);
+    h->sh[s] = pick_shape(cfg->ensemble, h->f64, dims[s], h->ld[s]);
     if (h->sh[s].nwg > maxwg) maxwg = h->sh[s].nwg;
   }
   int rc = HD_OK;
@@ -1054,6 +1087,99 @@ int hd_lista_backward(hd_handle h, int32_t L, const float* a,
   }
   h->hint = -1;
   return rc;
+}
+
+int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
+                int32_t count, int32_t k, void* stream, double* report) {
+  if (ensemble != HD_GINIBRE && ensemble != HD_HAAR) return HD_ERR_INVALID;
+  if (storage != HD_F32 && storage != HD_F64) return HD_ERR_INVALID;
+  if (!lengths || count < 1 || k < 2) return HD_ERR_INVALID;
+  for (int i = 0; i < count; ++i)
+    if (lengths[i] < k || lengths[i] > ((int64_t)1 << 31)) return HD_ERR_INVALID;
+  const int f64 = storage == HD_F64;
+  const int cands[3] = {1, 2, 4};
+  std::vector<std::pair<int64_t, int>> table;
+  for (int i = 0; i < count; ++i) {
+    const int64_t n = lengths[i];
+    hd_config cfg;
+    std::memset(&cfg, 0, sizeof(cfg));
+    cfg.ensemble = ensemble;
+    cfg.storage = storage;
+    cfg.m = cfg.n = n;
+    cfg.t_max = k;
+    cfg.sigma = 1.0 / std::sqrt((double)n);
+    cfg.stream = stream;
+    g_force_cpt = 1;
+    hd_handle h = nullptr;
+    int rc = hd_init(&cfg, &h);
+    g_force_cpt = 0;
+    if (rc) return rc;
+    void* x1 = nullptr;
+    rc = dalloc(h, &x1, (size_t)h->es * (size_t)n);
+    // any finite nonzero start vector: every byte 0x3F
+    if (!rc && hipMemsetAsync(x1, 0x3F, (size_t)h->es * (size_t)n,
+                              h->stream) != hipSuccess)
+      rc = hip_fail(hipGetLastError());
+    // Haar: queries with Q only; Gaussian: Q and Q' alternating, so both
+    // sides grow
+    hd_dynamics dyn;
+    dyn.kind = HD_DYN_TANH;
+    dyn.pattern = ensemble == HD_HAAR ? HD_PATTERN_Q : HD_PATTERN_ALT;
+    dyn.a = 1.0;
+    dyn.b = 0.5;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess ||
+                hipEventCreate(&e1) != hipSuccess))
+      rc = hip_fail(hipGetLastError());
+    double best = 0.0;
+    int best_cpt = 1;
+    for (int c = 0; c < 3 && !rc; ++c) {
+      for (int s = 0; s < 2; ++s) h->sh[s] = shape_of(h->ld[s], cands[c]);
+      // one untimed trajectory, then three timed ones (each a fresh Q)
+      float ms = 0.f;
+      for (int rep = 0; rep < 4 && !rc; ++rep) {
+        rc = hd_reset(h, 0, (uint32_t)rep);
+        if (!rc && rep == 1 && hipEventRecord(e0, h->stream) != hipSuccess)
+          rc = hip_fail(hipGetLastError());
+        if (!rc) rc = hd_run(h, &dyn, k, x1, nullptr, nullptr, nullptr, nullptr);
+      }
+      if (!rc && hipEventRecord(e1, h->stream) != hipSuccess)
+        rc = hip_fail(hipGetLastError());
+      if (!rc && hipEventSynchronize(e1) != hipSuccess)
+        rc = hip_fail(hipGetLastError());
+      if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = hip_fail(hipGetLastError());
+      const double us = 1e3 * ms / 3.0;
+      if (report) report[3 * i + c] = us;
+      if (!rc && (c == 0 || us < best)) {
+        best = us;
+        best_cpt = cands[c];
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    hd_free(h);
+    if (rc) return rc;
+    table.push_back({n, best_cpt});
+  }
+  std::sort(table.begin(), table.end());
+  g_tuned[ensemble == HD_HAAR ? 1 : 0][f64] = table;
+  return HD_OK;
+}
+
+int hd_shape_rule(int32_t ensemble, int32_t storage, int64_t n, int32_t* cpt) {
+  if (ensemble != HD_GINIBRE && ensemble != HD_HAAR) return HD_ERR_INVALID;
+  if ((storage != HD_F32 && storage != HD_F64) || n < 1 || !cpt)
+    return HD_ERR_INVALID;
+  const int64_t ld = round_up(n, kChunk);
+  *cpt = pick_shape(ensemble, storage == HD_F64, n, ld).cpt;
+  return HD_OK;
+}
+
+int hd_autotune_clear(void) {
+  for (auto& e : g_tuned)
+    for (auto& t : e) t.clear();
+  return HD_OK;
 }
 
 int hd_profile(hd_handle h, int32_t enable) {

@@ -312,7 +312,8 @@ struct LaunchEvents {
 };
 
 // Largest k for the data pass's z prologue (its LDS holds 2 * kZproMax
-// doubles); only one-chunk shapes use it.
+// doubles); shapes of up to two chunks per workgroup use it (and the
+// Gaussian random pass's reflector-step prologue).
 constexpr int kZproMax = 512;
 
 int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s,

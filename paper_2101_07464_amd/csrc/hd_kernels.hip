@@ -559,7 +559,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
   if (a.pf) lane_rows<CPT>(gpf, gn);
   double* out = a.partials + (int64_t)blk * a.pstride;
   const double* z = a.z;
-  if constexpr (MODE == kPassData && CPT == 1) {
+  if constexpr (MODE == kPassData && CPT <= 2) {
     // z = T' w (and T column kp) computed by every workgroup (see zpro)
     __shared__ double zl[kZproMax], tc[kZproMax];
     if (a.zpro) {
@@ -716,7 +716,7 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   const double* z2 = a.z2;
   double nu = 0.0;
   bool have_nu = false;
-  if constexpr (CPT == 1) {
+  if constexpr (CPT <= 2) {
     // the reflector step (as in gin_small_body), computed by every workgroup
     __shared__ double s1l[kZproMax], s2l[kZproMax], z1l[kZproMax],
         z2l[kZproMax], shr[3];

@@ -67,3 +67,40 @@ def test_null_arguments():
     assert L.hd_free(None) == _lib.HD_OK
     assert L.hd_run(None, None, 0, None, None, None, None, None) == \
         _lib.HD_ERR_INVALID
+
+
+@pytest.mark.skipif("HD_CPT" in os.environ, reason="HD_CPT overrides shapes")
+def test_builtin_shape_rule():
+    L = _lib.load()
+    cpt = ctypes.c_int32()
+    assert L.hd_autotune_clear() == _lib.HD_OK
+    for ens in (_lib.HD_GINIBRE, _lib.HD_HAAR):
+        for st in (_lib.HD_F32, _lib.HD_F64):
+            for n, want in [(1, 1), (65536, 1), ((1 << 18) - 1, 1),
+                            (1 << 18, 2), ((1 << 19) - 1, 2), (1 << 19, 4),
+                            (10 ** 7, 4)]:
+                assert L.hd_shape_rule(ens, st, n, ctypes.byref(cpt)) == \
+                    _lib.HD_OK
+                assert cpt.value == want, (ens, st, n)
+    assert L.hd_shape_rule(0, 5, 10, ctypes.byref(cpt)) == _lib.HD_ERR_INVALID
+    assert L.hd_shape_rule(2, 0, 10, ctypes.byref(cpt)) == _lib.HD_ERR_INVALID
+    assert L.hd_shape_rule(0, 0, 0, ctypes.byref(cpt)) == _lib.HD_ERR_INVALID
+    assert L.hd_shape_rule(0, 0, 10, None) == _lib.HD_ERR_INVALID
+
+
+def test_autotune_rejects_invalid_arguments():
+    L = _lib.load()
+    arr = (ctypes.c_int64 * 2)(4096, 1)
+    H, F32 = _lib.HD_HAAR, _lib.HD_F32
+    assert L.hd_autotune(H, F32, None, 1, 8, None, None) == \
+        _lib.HD_ERR_INVALID
+    assert L.hd_autotune(5, F32, arr, 1, 8, None, None) == \
+        _lib.HD_ERR_INVALID
+    assert L.hd_autotune(H, 7, arr, 1, 8, None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_autotune(H, F32, arr, 0, 8, None, None) == \
+        _lib.HD_ERR_INVALID
+    assert L.hd_autotune(H, F32, arr, 1, 1, None, None) == \
+        _lib.HD_ERR_INVALID
+    # the second length is shorter than the trajectory
+    assert L.hd_autotune(H, F32, arr, 2, 8, None, None) == \
+        _lib.HD_ERR_INVALID
