@@ -96,6 +96,33 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial);
 /* Change the stream used by later calls (hipStream_t, NULL = null stream). */
 int hd_set_stream(hd_handle h, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Checkpoint and resume.  The state of a handle after its last query is
+ * what Algorithms 1 and 2 carry from one query to the next: the stored
+ * reflectors of both sides (panels, T factors, tau, the norms, pivots and
+ * signs), the Gaussian ensemble's explicit basis vectors, the query
+ * counters, the Philox key, the sticky device flag and the data-independent
+ * dots already computed for the next query.
+ *
+ * hd_export: host_buf == NULL stores the required size in *size; otherwise
+ * *size is the capacity of host_buf (host memory, caller-owned), which
+ * receives the state (a self-describing byte block of that size).  Finishes
+ * the stream's pending work for the handle and synchronises it; the handle
+ * is unchanged and can continue.  Works also after a device error.
+ * Errors: HD_ERR_INVALID (h or size NULL, capacity too small: *size is set
+ * to the required size), HD_ERR_HIP.
+ *
+ * hd_import: creates a handle (as hd_init, on cfg->stream) holding an
+ * exported state; the next query continues the exported sequence exactly
+ * (same realisation of Q).  cfg must repeat the exporter's ensemble,
+ * storage, m, n, t_max (and sigma for the Gaussian ensemble); seed and
+ * trial come from the state.  The launch shape may differ from the
+ * exporter's.  Errors: HD_ERR_INVALID (mismatching cfg, malformed or short
+ * buffer), HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_export(hd_handle h, void* host_buf, size_t* size);
+int hd_import(const hd_config* cfg, const void* host_buf, size_t size,
+              hd_handle* out);
+
 /* Copy to host, for the first `count` reflectors of one side
  * (side 0 = R, acting on R^n; side 1 = L, acting on R^m): the norm nu of the
  * vector it was built from, that vector's first entry (the pivot) and the

@@ -40,7 +40,7 @@ class LazyMatrix:
     """
 
     def __init__(self, ensemble, n, m=None, t_max=None, seed=0, trial=0,
-                 sigma=1.0, dtype=None, device="cuda:0"):
+                 sigma=1.0, dtype=None, device="cuda:0", state=None):
         torch = _torch()
         m = n if m is None else m
         t_max = min(m, n) if t_max is None else t_max
@@ -55,9 +55,30 @@ class LazyMatrix:
                             _stream_ptr(self.device))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _lib.check(_lib.load().hd_init(ctypes.byref(cfg), ctypes.byref(h)),
-                       "hd_init")
+            if state is None:
+                _lib.check(_lib.load().hd_init(ctypes.byref(cfg),
+                                               ctypes.byref(h)), "hd_init")
+            else:
+                import numpy as np
+                buf = np.ascontiguousarray(state, dtype=np.uint8)
+                _lib.check(_lib.load().hd_import(
+                    ctypes.byref(cfg), buf.ctypes.data_as(ctypes.c_void_p),
+                    buf.nbytes, ctypes.byref(h)), "hd_import")
         self._h = h
+
+    def export_state(self):
+        """The handle's state as a numpy uint8 array (``hd_export``); pass it
+        as ``state=`` with the same ensemble, sizes, t_max, sigma and dtype
+        to continue the same realisation in a new handle."""
+        import numpy as np
+        L = _lib.load()
+        self._sync_stream()
+        size = ctypes.c_size_t(0)
+        _lib.check(L.hd_export(self._h, None, ctypes.byref(size)), "hd_export")
+        buf = np.empty(size.value, dtype=np.uint8)
+        _lib.check(L.hd_export(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(size)), "hd_export")
+        return buf
 
     def close(self):
         h = getattr(self, "_h", None)

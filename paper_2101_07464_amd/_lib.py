@@ -35,7 +35,7 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_batch_init", "hd_batch_run", "hd_batch_status",
            "hd_batch_set_stream", "hd_batch_free", "hd_lista_forward",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
-           "hd_autotune_clear"]
+           "hd_autotune_clear", "hd_export", "hd_import"]
 
 
 class HDConfig(ctypes.Structure):
@@ -108,6 +108,8 @@ def load():
         "hd_autotune": (i32, [i32, i32, P(i64), i32, i32, vp, P(dbl)]),
         "hd_shape_rule": (i32, [i32, i32, i64, P(i32)]),
         "hd_autotune_clear": (i32, []),
+        "hd_export": (i32, [vp, vp, P(ctypes.c_size_t)]),
+        "hd_import": (i32, [P(HDConfig), vp, ctypes.c_size_t, P(vp)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

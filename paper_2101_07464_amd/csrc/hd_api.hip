@@ -705,6 +705,132 @@ int query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
 
 }  // namespace
 
+// ------------------------------------------------------ checkpoint state --
+//
+// Layout of an exported state (host byte order): StateHeader, then for each
+// side s = 0 (R), 1 (L): vcols[s] panel columns of dim[s] entries (storage
+// type), T (t_max^2 FP64, column-major), tau, nu, pivot, sign (t_max FP64
+// each), pi (t_max + 1 FP64), the reduced results of the side's last pass
+// (pstride FP64); then, for the Gaussian ensemble, bcols[s] explicit basis
+// columns of dim[s] entries per side.
+
+namespace {
+
+constexpr char kStateMagic[8] = {'H', 'D', 'S', 'T', 'A', 'T', 'E', '1'};
+
+struct StateHeader {
+  char magic[8];
+  int32_t ensemble, storage, t_max, pstride;
+  int64_t m, n;
+  uint32_t seed, trial;
+  double sigma;
+  int32_t t, r, l, flag;
+  int32_t pf_step[2], pending[2];
+  int32_t vcols[2], bcols[2];
+  uint64_t total_bytes;
+};
+
+size_t state_bytes(const StateHeader& H) {
+  const size_t es = H.storage == HD_F64 ? 8 : 4;
+  const size_t tm = (size_t)H.t_max;
+  const int64_t dims[2] = {H.n, H.m};
+  size_t b = sizeof(StateHeader);
+  for (int s = 0; s < 2; ++s) {
+    b += es * (size_t)dims[s] * (size_t)H.vcols[s];
+    b += 8 * (tm * tm + 5 * tm + 1 + (size_t)H.pstride);
+    b += es * (size_t)dims[s] * (size_t)H.bcols[s];
+  }
+  return b;
+}
+
+StateHeader header_of(const hd_ctx* h) {
+  StateHeader H;
+  std::memset(&H, 0, sizeof(H));
+  std::memcpy(H.magic, kStateMagic, sizeof(kStateMagic));
+  H.ensemble = h->cfg.ensemble;
+  H.storage = h->cfg.storage;
+  H.t_max = h->cfg.t_max;
+  H.pstride = h->pstride;
+  H.m = h->cfg.m;
+  H.n = h->cfg.n;
+  H.seed = h->cfg.seed;
+  H.trial = h->cfg.trial;
+  H.sigma = h->cfg.ensemble == HD_GINIBRE ? h->cfg.sigma : 0.0;
+  H.t = h->t;
+  H.r = h->r;
+  H.l = h->l;
+  for (int s = 0; s < 2; ++s) {
+    H.pf_step[s] = h->pf_step[s];
+    H.pending[s] = h->pending[s];
+  }
+  if (h->cfg.ensemble == HD_HAAR) {
+    H.vcols[0] = H.vcols[1] = h->t;
+  } else {
+    // reflectors: R gets one per Q-query, L one per Q'-query; explicit
+    // basis: B[0] holds v of Q'-queries, B[1] u of Q-queries
+    H.vcols[0] = h->r;
+    H.vcols[1] = h->l;
+    H.bcols[0] = h->l;
+    H.bcols[1] = h->r;
+  }
+  H.total_bytes = 0;
+  H.total_bytes = state_bytes(H);
+  return H;
+}
+
+// Copies `cols` columns of `rows` entries between a panel (leading dimension
+// ld) and a packed host block, synchronously.
+int copy_cols(void* dev, int64_t ld, char* host, int64_t rows, int cols,
+              size_t es, bool to_host) {
+  if (cols <= 0 || rows <= 0) return HD_OK;
+  const size_t w = es * (size_t)rows;
+  hipError_t e;
+  if (to_host)
+    e = hipMemcpy2D(host, w, dev, es * (size_t)ld, w, (size_t)cols,
+                    hipMemcpyDeviceToHost);
+  else
+    e = hipMemcpy2D(dev, es * (size_t)ld, host, w, w, (size_t)cols,
+                    hipMemcpyHostToDevice);
+  return e == hipSuccess ? HD_OK : hip_fail(e);
+}
+
+int copy_block(void* dev, char* host, size_t bytes, bool to_host) {
+  const hipError_t e =
+      to_host ? hipMemcpy(host, dev, bytes, hipMemcpyDeviceToHost)
+              : hipMemcpy(dev, host, bytes, hipMemcpyHostToDevice);
+  return e == hipSuccess ? HD_OK : hip_fail(e);
+}
+
+// Moves every array of the state between the handle and `buf` (after the
+// header), in the documented order.
+int move_state(hd_ctx* h, const StateHeader& H, char* buf, bool to_host) {
+  char* p = buf + sizeof(StateHeader);
+  const size_t es = (size_t)h->es;
+  const size_t tm = (size_t)h->cfg.t_max;
+  int rc = HD_OK;
+  for (int s = 0; s < 2 && !rc; ++s) {
+    PanelDev& P = h->P[s];
+    rc = copy_cols(P.V, P.ld, p, h->dim[s], H.vcols[s], es, to_host);
+    p += es * (size_t)h->dim[s] * (size_t)H.vcols[s];
+    void* arrays[6] = {P.T, P.tau, P.nu, P.piv, P.sgn, P.pi};
+    const size_t sizes[6] = {tm * tm, tm, tm, tm, tm, tm + 1};
+    for (int a = 0; a < 6 && !rc; ++a) {
+      rc = copy_block(arrays[a], p, 8 * sizes[a], to_host);
+      p += 8 * sizes[a];
+    }
+    if (!rc) rc = copy_block(P.red, p, 8 * (size_t)h->pstride, to_host);
+    p += 8 * (size_t)h->pstride;
+  }
+  for (int s = 0; s < 2 && !rc; ++s) {
+    if (H.bcols[s] <= 0) continue;
+    rc = copy_cols(h->B[s], h->ld[s], p, h->dim[s], H.bcols[s], es, to_host);
+    p += es * (size_t)h->dim[s] * (size_t)H.bcols[s];
+  }
+  return rc;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hd_strerror(int code) {
@@ -871,6 +997,102 @@ int hd_counts(hd_handle h, int32_t* t, int32_t* r, int32_t* l) {
   if (t) *t = h->t;
   if (r) *r = h->r;
   if (l) *l = h->l;
+  return HD_OK;
+}
+
+int hd_export(hd_handle h, void* host_buf, size_t* size) {
+  if (!h || !size) return HD_ERR_INVALID;
+  const StateHeader H0 = header_of(h);
+  if (!host_buf) {
+    *size = (size_t)H0.total_bytes;
+    return HD_OK;
+  }
+  if (*size < H0.total_bytes) {
+    *size = (size_t)H0.total_bytes;
+    return HD_ERR_INVALID;
+  }
+  // finish the deferred reduction of the last random pass, so that every
+  // reduced result is in place
+  if (h->deferred.rg.count[0] + h->deferred.rg.count[1] +
+          h->deferred.rg.count[2] > 0) {
+    LCHK(launch_reduce(h->deferred, no_job(), h->stream));
+    h->deferred = no_job();
+  }
+  HIPC(hipStreamSynchronize(h->stream));
+  StateHeader H = H0;
+  int flag = 0;
+  HIPC(hipMemcpy(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost));
+  H.flag = flag;
+  std::memcpy(host_buf, &H, sizeof(H));
+  const int rc = move_state(h, H, (char*)host_buf, true);
+  if (rc == HD_OK) *size = (size_t)H.total_bytes;
+  return rc;
+}
+
+int hd_import(const hd_config* cfg, const void* host_buf, size_t size,
+              hd_handle* out) {
+  if (!cfg || !host_buf || !out) return HD_ERR_INVALID;
+  *out = nullptr;
+  if (size < sizeof(StateHeader)) return HD_ERR_INVALID;
+  StateHeader H;
+  std::memcpy(&H, host_buf, sizeof(H));
+  if (std::memcmp(H.magic, kStateMagic, sizeof(kStateMagic)) != 0)
+    return HD_ERR_INVALID;
+  if (H.ensemble != cfg->ensemble || H.storage != cfg->storage ||
+      H.t_max != cfg->t_max || H.m != cfg->m || H.n != cfg->n)
+    return HD_ERR_INVALID;
+  if (H.ensemble == HD_GINIBRE && H.sigma != cfg->sigma)
+    return HD_ERR_INVALID;
+  if (H.t < 0 || H.t > H.t_max || H.r < 0 || H.l < 0 || H.r > H.t ||
+      H.l > H.t)
+    return HD_ERR_INVALID;
+  hd_config c = *cfg;
+  c.seed = H.seed;
+  c.trial = H.trial;
+  hd_handle h = nullptr;
+  int rc = hd_init(&c, &h);
+  if (rc) return rc;
+  // the header must describe exactly this handle's state arrays
+  StateHeader want = header_of(h);
+  want.t = H.t;
+  want.r = H.r;
+  want.l = H.l;
+  if (H.ensemble == HD_HAAR) {
+    want.vcols[0] = want.vcols[1] = H.t;
+  } else {
+    want.vcols[0] = want.bcols[1] = H.r;
+    want.vcols[1] = want.bcols[0] = H.l;
+  }
+  want.total_bytes = 0;
+  want.total_bytes = state_bytes(want);
+  if (H.pstride != want.pstride || H.vcols[0] != want.vcols[0] ||
+      H.vcols[1] != want.vcols[1] || H.bcols[0] != want.bcols[0] ||
+      H.bcols[1] != want.bcols[1] || H.total_bytes != want.total_bytes ||
+      size < H.total_bytes) {
+    hd_free(h);
+    return HD_ERR_INVALID;
+  }
+  for (int s = 0; s < 2; ++s)
+    if (H.pending[s] < -1 || H.pending[s] >= H.vcols[s] || H.pf_step[s] < 0) {
+      hd_free(h);
+      return HD_ERR_INVALID;
+    }
+  rc = move_state(h, H, (char*)host_buf, false);
+  if (!rc && hipMemcpy(h->flag, &H.flag, sizeof(int),
+                       hipMemcpyHostToDevice) != hipSuccess)
+    rc = hip_fail(hipGetLastError());
+  if (rc) {
+    hd_free(h);
+    return rc;
+  }
+  h->t = H.t;
+  h->r = H.r;
+  h->l = H.l;
+  for (int s = 0; s < 2; ++s) {
+    h->pf_step[s] = H.pf_step[s];
+    h->pending[s] = H.pending[s];
+  }
+  *out = h;
   return HD_OK;
 }
 

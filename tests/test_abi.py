@@ -104,3 +104,54 @@ def test_autotune_rejects_invalid_arguments():
     # the second length is shorter than the trajectory
     assert L.hd_autotune(H, F32, arr, 2, 8, None, None) == \
         _lib.HD_ERR_INVALID
+
+
+def _state_header(**kw):
+    """A state header as hd_export writes it (host byte order)."""
+    import struct
+    f = dict(magic=b"HDSTATE1", ensemble=_lib.HD_HAAR, storage=_lib.HD_F32,
+             t_max=8, pstride=20, m=64, n=64, seed=0, trial=0, sigma=0.0,
+             t=2, r=2, l=2, flag=0, pf=(0, 0), pending=(-1, -1),
+             vcols=(2, 2), bcols=(0, 0), total=1 << 20)
+    f.update(kw)
+    return struct.pack("<8s4i2q2Id4i2i2i2i2iQ", f["magic"], f["ensemble"],
+                       f["storage"], f["t_max"], f["pstride"], f["m"], f["n"],
+                       f["seed"], f["trial"], f["sigma"], f["t"], f["r"],
+                       f["l"], f["flag"], *f["pf"], *f["pending"],
+                       *f["vcols"], *f["bcols"], f["total"])
+
+
+def test_state_header_size():
+    assert len(_state_header()) == 112
+
+
+@pytest.mark.parametrize("kw", [
+    dict(magic=b"HDSTATE0"),
+    dict(m=65, n=65),              # sizes differ from cfg
+    dict(t_max=9),
+    dict(storage=_lib.HD_F64),
+    dict(ensemble=_lib.HD_GINIBRE),
+    dict(t=9),                     # beyond t_max
+    dict(r=3),                     # more reflectors than queries
+])
+def test_import_rejects_malformed_state(kw):
+    L = _lib.load()
+    buf = _state_header(**kw) + bytes(256)
+    h = ctypes.c_void_p()
+    rc = L.hd_import(ctypes.byref(_cfg()), buf, len(buf), ctypes.byref(h))
+    assert rc == _lib.HD_ERR_INVALID
+    assert not h.value
+
+
+def test_export_import_null_arguments():
+    L = _lib.load()
+    size = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    assert L.hd_export(None, None, ctypes.byref(size)) == _lib.HD_ERR_INVALID
+    assert L.hd_import(None, b"x" * 200, 200, ctypes.byref(h)) == \
+        _lib.HD_ERR_INVALID
+    assert L.hd_import(ctypes.byref(_cfg()), None, 200, ctypes.byref(h)) == \
+        _lib.HD_ERR_INVALID
+    # shorter than the header
+    assert L.hd_import(ctypes.byref(_cfg()), b"HDSTATE1", 8,
+                       ctypes.byref(h)) == _lib.HD_ERR_INVALID
