@@ -132,3 +132,31 @@ def test_autograd_and_finite_difference():
             print("eps %.0e FD %.10e analytic %.10e rel %.1e" %
                   (eps, fd, an, rel[-1]))
         assert rel[1] <= 1e-5
+
+
+def test_full_size_layer_replay_fp32():
+    """One trial of the differentiated workload at its full size (n =
+    262144, m = 131072, 50 layers, FP32, in the launch shapes the benchmark
+    uses): every layer against the oracle on the GPU's own input, and the
+    gradient against the oracle's reverse pass on the GPU's u_t, v_t."""
+    n, m, L = 262144, 131072, 50
+    A, orc, xs, y, a, th = _setup(n, m, L, torch.float32)
+    X, U, V = A.lista_forward(a, th, torch.zeros(n, device=DEV), y)
+    g = 2.0 * (X[-1] - torch.from_numpy(xs).to(DEV, torch.float32))
+    ga, gt, _ = A.lista_backward(a, th, U, V, g)
+    torch.cuda.synchronize()
+    assert A.status() == 0
+    Xg, Ug, Vg = (t.double().cpu().numpy() for t in (X, U, V))
+    yo = y.double().cpu().numpy()
+    worst = 0.0
+    for t in range(L):
+        r = orc.query(Xg[t], False)
+        u = orc.query(yo - r, True)
+        worst = max(worst, relerr(Ug[t], u),
+                    relerr(Vg[t], Xg[t] + float(a[t]) * u))
+    dao, dto, _ = oracle.lista_backward(orc, g.double().cpu().numpy(),
+                                        a.astype(np.float64),
+                                        th.astype(np.float64), Ug, Vg)
+    eg = max(relerr(ga.cpu(), dao), relerr(gt.cpu(), dto))
+    print("full-size ISTA layer replay %.1e gradient %.1e" % (worst, eg))
+    assert worst < 1e-4 and eg < 1e-4

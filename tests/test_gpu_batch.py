@@ -92,3 +92,46 @@ def test_batch_rejects_bad_input():
     B = hd.HaarBatch([(300, 4, 0, 0)], device=DEV)
     with pytest.raises(ValueError):
         B.run([torch.zeros(299, device=DEV)], "tanh", 2.0, 0.0)
+
+
+def test_full_batch_4096_sampled_and_invariants():
+    """The batched workload at its full size (4096 Haar trials, n
+    log-uniform in [1e3, 1e5], T uniform in [10, 200], FP32, tanh(2y)), as
+    the benchmark launches it.  Every trial: the map x_{t+1} = tanh(2 y_t)
+    and the isometry ||y_t|| = ||x_t|| at every step; six sampled trials
+    (largest n, longest T, smallest n, three seeded picks): every answer
+    against the oracle (mode B)."""
+    nb, Tb = inputs.ragged_batch(4096)
+    trials = [(int(n), int(T), 0, b) for b, (n, T) in enumerate(zip(nb, Tb))]
+    B = hd.HaarBatch(trials, dtype=torch.float32, device=DEV)
+    x1 = [torch.from_numpy(inputs.x1_normal(n, seed=0, trial=b)).to(
+        DEV, torch.float32) for n, T, _, b in trials]
+    X, Y = B.run(x1, "tanh", 2.0, 0.0, record=True)
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    del B
+    worst_map = worst_iso = 0.0
+    for Xi, Yi in zip(X, Y):
+        xd, yd = Xi.double(), Yi.double()
+        d = (xd[1:] - torch.tanh(2.0 * yd)).abs().max() / \
+            xd[1:].abs().max().clamp_min(1e-300)
+        worst_map = max(worst_map, float(d))
+        nx, ny = xd[:-1].norm(dim=1), yd.norm(dim=1)
+        worst_iso = max(worst_iso, float(((ny - nx) / nx).abs().max()))
+    n_arr, T_arr = np.array(nb), np.array(Tb)
+    pick = {int(n_arr.argmax()), int(T_arr.argmax()), int(n_arr.argmin())}
+    pick |= set(int(i) for i in np.random.default_rng(11).choice(
+        len(trials), 3, replace=False))
+    worst = 0.0
+    for i in sorted(pick):
+        n, T, s, k = trials[i]
+        Xi = X[i].double().cpu().numpy()
+        Yi = Y[i].double().cpu().numpy()
+        orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=s, trial=k)
+        ref = oracle.replay(orc, Xi[:-1], [False] * T)
+        worst = max(worst, max(relerr(y, r) for y, r in zip(Yi, ref)))
+    print("full batch: map %.2e, isometry %.2e, sampled mode B %.2e (%s)" %
+          (worst_map, worst_iso, worst, sorted(pick)))
+    assert worst_map < 1e-6
+    assert worst_iso < 1e-5
+    assert worst < 1e-4
