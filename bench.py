@@ -233,7 +233,10 @@ def main_batch(args):
                    "algorithmic_bytes_per_step": by},
         "roofline": {"bound": "hbm", "kernel": "whole batched step",
                      "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(C3["name"],
+                                                 "whole batched step"),
+                     "traffic_unit": "bytes per batched step"},
         "plain_per_trial": {"value": plain, "unit": "elem-updates/s",
                             "sample": "%d of the trials, one handle each "
                                       "(hd_run), plan with the same kernels"
