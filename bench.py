@@ -266,6 +266,76 @@ def tune_shapes(args, hd, ens, lengths, dtype, k):
     return out
 
 
+GOE = dict(name="goe_n65536_K50_linear_fp32", n=65536, K=50)
+
+
+def main_goe(args):
+    """GOE queries (two queries of the lazy Gaussian each): x_{t+1} = G x_t
+    for K steps, G ~ GOE(n) / sqrt(n), FP32."""
+    import ctypes
+    import torch
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import _lib, inputs
+    dev = "cuda:0"
+    n, K = GOE["n"], GOE["K"]
+    shape = tune_shapes(args, hd, hd.GINIBRE, [n], torch.float32, 32)
+    G = hd.LazyGOE(n, t_max=2 * K, seed=0, scale=1.0 / np.sqrt(n),
+                   device=dev)
+    x1 = torch.from_numpy(inputs.x1_normal(n, seed=0)).to(dev, torch.float32)
+    buf = [torch.empty_like(x1), torch.empty_like(x1)]
+    L = _lib.load()
+    G._sync_stream()
+
+    def step(i):
+        G.reset(0, i)
+        src = x1
+        for t in range(K):
+            dst = buf[t % 2]
+            _lib.check(L.hd_goe_step(G._h, ctypes.c_void_p(src.data_ptr()),
+                                     ctypes.c_void_p(dst.data_ptr())),
+                       "hd_goe_step")
+            src = dst
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if G.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    G.profile(True)
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    kinds = {k: G.profile_read(k) for k in (0, 1, 2)}
+    G.profile(False)
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, launches, nbytes = kinds[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    W = nominal_work(n, 2 * K)
+    out = {
+        "metric": METRIC, "value": W * args.steps / elapsed,
+        "unit": "elem-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": GOE["name"], "n": n, "goe_queries": K,
+                   "queries_of_Q": 2 * K, "elem_updates_per_step": W,
+                   "launch_shape": shape},
+        "roofline": {"bound": "hbm", "kernel": KIND_NAMES[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": launches,
+                     "avg_launch_us": ms * 1e3 / max(launches, 1),
+                     "algorithmic_bytes_per_launch":
+                         nbytes / max(launches, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main_adjoint(args):
     import torch
     import paper_2101_07464_amd as hd
@@ -350,7 +420,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2",
-                    choices=sorted(list(WORKLOADS) + ["c3", "c5"]))
+                    choices=sorted(list(WORKLOADS) + ["c3", "c5", "goe"]))
     ap.add_argument("--c5-trials", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
@@ -372,6 +442,9 @@ def main():
         return
     if args.workload == "c5":
         main_adjoint(args)
+        return
+    if args.workload == "goe":
+        main_goe(args)
         return
 
     import torch

@@ -97,6 +97,20 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial);
 int hd_set_stream(hd_handle h, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Gaussian orthogonal ensemble from the Gaussian one (section "Other Random
+ * Matrix Ensembles"): for Q with i.i.d. N(0, s^2) entries, (Q + Q')/sqrt(2)
+ * is GOE of scale s (diagonal N(0, 2 s^2), off-diagonal N(0, s^2)).
+ * hd_goe_step answers y = Q x + Q' x with two queries on a square Gaussian
+ * handle (Q x first, then Q' x with the sum formed in its epilogue), so a
+ * handle created with sigma = s / sqrt(2) answers y = G x for G ~ s GOE(n),
+ * the paper's y = (Q' x + Q x) / sqrt(2) for the scale-s Q.  Each call uses
+ * two of the handle's t_max queries (one reflector per side).  x, y: device
+ * vectors of n entries (storage type), not aliased.  Errors: HD_ERR_INVALID
+ * (not a square Gaussian handle, null or aliased pointers),
+ * HD_ERR_CAPACITY, HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_goe_step(hd_handle h, const void* x, void* y);
+
+/* ------------------------------------------------------------------------
  * Checkpoint and resume.  The state of a handle after its last query is
  * what Algorithms 1 and 2 carry from one query to the next: the stored
  * reflectors of both sides (panels, T factors, tau, the norms, pivots and

@@ -218,6 +218,14 @@ def run_trajectory(orc, x1, T, dyn, a, b, pattern="Q", x0=None,
     return np.array(X), np.array(Y)
 
 
+def goe_query(orc, x):
+    """y = G x for G = (Q + Q') / sqrt(2) ~ sigma GOE(n) (section "Other
+    Random Matrix Ensembles"): the lazy square Gaussian Q answers
+    y_hat = Q x, then y = (Q' x + y_hat) / sqrt(2)."""
+    y_hat = orc.query(np.asarray(x, np.float64), False)
+    return (orc.query(np.asarray(x, np.float64), True) + y_hat) / np.sqrt(2.0)
+
+
 def replay(orc, xs, transposes):
     """Mode B: answer the given query vectors in order; returns the outputs."""
     return [orc.query(np.asarray(x, np.float64), bool(tr))

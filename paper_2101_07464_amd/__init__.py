@@ -66,6 +66,19 @@ class LazyMatrix:
                     buf.nbytes, ctypes.byref(h)), "hd_import")
         self._h = h
 
+    def goe_mv(self, x):
+        """y = Q x + Q' x (``hd_goe_step``): G x for G = (Q + Q') of a square
+        Gaussian handle, two queries.  See ``LazyGOE``."""
+        torch = _torch()
+        x = self._vec(x, self.n)
+        y = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_goe_step(self._h,
+                                           ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr())),
+                   "hd_goe_step")
+        return y
+
     def export_state(self):
         """The handle's state as a numpy uint8 array (``hd_export``); pass it
         as ``state=`` with the same ensemble, sizes, t_max, sigma and dtype
@@ -399,3 +412,28 @@ def shape_rule(ensemble, n, dtype=None):
 def autotune_clear():
     """Drop every tuned shape (back to the built-in rule)."""
     _lib.check(_lib.load().hd_autotune_clear(), "hd_autotune_clear")
+
+
+class LazyGOE(LazyMatrix):
+    """Lazy n x n matrix G ~ scale * GOE(n) (symmetric; diagonal entries
+    N(0, 2 scale^2), off-diagonal N(0, scale^2)), built from a lazy Gaussian
+    Q with N(0, scale^2 / 2) entries as G = Q + Q'.  ``mv`` answers G x with
+    two queries of Q, so t_max counts queries of Q (two per call)."""
+
+    def __init__(self, n, t_max=None, seed=0, trial=0, scale=1.0, dtype=None,
+                 device="cuda:0"):
+        import math
+        super().__init__(GINIBRE, n, t_max=t_max, seed=seed, trial=trial,
+                         sigma=scale / math.sqrt(2.0), dtype=dtype,
+                         device=device)
+        self.scale = scale
+
+    def mv(self, x):
+        return self.goe_mv(x)
+
+    def rmv(self, x):
+        return self.goe_mv(x)
+
+    def run(self, *args, **kwargs):
+        raise TypeError("LazyGOE answers single queries (mv); the built-in "
+                        "trajectories run on LazyMatrix")

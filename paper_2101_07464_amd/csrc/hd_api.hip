@@ -1215,6 +1215,30 @@ static int ista_buffers(hd_ctx* h) {
 
 // Room for `nq` more queries, pq of them Q-queries (Ginibre also needs
 // r <= n and l <= m).
+int hd_goe_step(hd_handle h, const void* x, void* y) {
+  if (!h || !x || !y || x == y) return HD_ERR_INVALID;
+  if (h->cfg.ensemble != HD_GINIBRE || h->cfg.m != h->cfg.n)
+    return HD_ERR_INVALID;
+  if (h->t + 2 > h->cfg.t_max) return HD_ERR_CAPACITY;
+  if ((int64_t)h->r >= h->dim[0] || (int64_t)h->l >= h->dim[1])
+    return HD_ERR_CAPACITY;
+  int rc = ista_buffers(h);  // two work vectors: Q x and Q' x
+  if (rc) return rc;
+  void* qx = h->ista[0];
+  void* qtx = h->ista[1];
+  h->hint = 1;
+  rc = query(h, 0, x, qx, 0, no_dyn());
+  h->hint = -1;
+  if (rc) return rc;
+  // y = Q x + Q' x, formed in the second query's epilogue
+  DynFuse f = no_dyn();
+  f.kind = kDynAxpy;
+  f.a = -1.0;
+  f.x = qx;
+  f.xnext = y;
+  return query(h, 1, x, qtx, 0, f);
+}
+
 static int ista_room(const hd_ctx* h, int nq, int pq) {
   if ((int64_t)h->t + nq > h->cfg.t_max) return HD_ERR_CAPACITY;
   if (h->cfg.ensemble == HD_GINIBRE &&

@@ -236,6 +236,15 @@ def test_ginibre_exact_reconstruction(m, n):
         hist.append((tr, x, orc.query(x, tr)))
     t, r, l = orc.counts()
     assert t == T and r + l == T
+    for _ in range(2):
+        Qr = _ginibre_rec(orc, m, n, sig, rng.standard_normal((m, n)))
+        for tr, x, y in hist:
+            assert np.allclose((Qr.T if tr else Qr) @ x, y, atol=1e-12)
+
+
+def _ginibre_rec(orc, m, n, sig, W):
+    """sigma (sum_i u_i v_i' + L_1..L_l Z_{1:l} W Z_{1:r} R_r..R_1)."""
+    t, r, l = orc.counts()
     S = np.zeros((m, n))
     for i in range(1, t + 1):
         u, v = orc.basis(i)
@@ -248,11 +257,48 @@ def test_ginibre_exact_reconstruction(m, n):
         Rm = reflector_matrix(n, orc.reflector(SIDE_R, i)) @ Rm
     Zl = np.diag(np.r_[np.zeros(l), np.ones(m - l)])
     Zr = np.diag(np.r_[np.zeros(r), np.ones(n - r)])
+    return sig * (S + Lm @ Zl @ W @ Zr @ Rm)
+
+
+def test_goe_exact_reconstruction():
+    """Section "Other Random Matrix Ensembles": the GOE answers are those of
+    the symmetric G = (Q_rec + Q_rec')/sqrt(2), for every completion W of
+    the lazy Gaussian Q (mixed with plain queries of Q in between)."""
+    n, sig = 11, 1.3
+    rng = np.random.default_rng(5)
+    orc = HDOracle(GINIBRE, n, seed=4, trial=2, sigma=sig)
+    goe, plain = [], []
+    for s in range(4):
+        x = rng.standard_normal(n)
+        goe.append((x, oracle.goe_query(orc, x)))
+        if s == 1:
+            z = rng.standard_normal(n)
+            plain.append((z, orc.mv(z)))
+    assert orc.counts()[0] == 9
     for _ in range(2):
-        W = rng.standard_normal((m, n))
-        Qr = sig * (S + Lm @ Zl @ W @ Zr @ Rm)
-        for tr, x, y in hist:
-            assert np.allclose((Qr.T if tr else Qr) @ x, y, atol=1e-12)
+        Qr = _ginibre_rec(orc, n, n, sig, rng.standard_normal((n, n)))
+        G = (Qr + Qr.T) / np.sqrt(2.0)
+        for x, y in goe:
+            assert np.allclose(G @ x, y, atol=1e-12)
+        for z, y in plain:
+            assert np.allclose(Qr @ z, y, atol=1e-12)
+
+
+def test_goe_entry_variances():
+    """G ~ sigma GOE(n): the first answer to x = e_j is column j of G, with
+    G_jj ~ N(0, 2 sigma^2) and G_ij ~ N(0, sigma^2) for i != j."""
+    n, sig, trials, j = 6, 0.7, 4000, 2
+    e = np.zeros(n)
+    e[j] = 1.0
+    cols = np.array([oracle.goe_query(
+        HDOracle(GINIBRE, n, seed=8, trial=k, sigma=sig), e)
+        for k in range(trials)])
+    sq = cols ** 2
+    for i in range(n):
+        want = (2.0 if i == j else 1.0) * sig ** 2
+        se = sq[:, i].std() / np.sqrt(trials)
+        assert abs(sq[:, i].mean() - want) < 5 * se, (i, sq[:, i].mean())
+    assert abs(cols.mean(axis=0)).max() < 5 * sig * np.sqrt(2.0 / trials)
 
 
 # ------------------------------------------------------- isometry (P4) ---
