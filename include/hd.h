@@ -110,6 +110,18 @@ int hd_set_stream(hd_handle h, void* stream);
  * HD_ERR_CAPACITY, HD_ERR_NOMEM, HD_ERR_HIP. */
 int hd_goe_step(hd_handle h, const void* x, void* y);
 
+/* Q = U S V with U, V independent Haar-orthogonal (two Haar handles of the
+ * same n, storage type and stream) and S = diag(s) (section "Other Random
+ * Matrix Ensembles", square case): transpose = 0 answers y = U (s .* (V x)),
+ * transpose = 1 answers y = Q' x = V' (s .* (U' x)); one query on each
+ * handle, the entrywise product formed in the first query's epilogue.
+ * s, x, y: device vectors of n entries (storage type); x and y not
+ * aliased.  Errors: HD_ERR_INVALID (not two distinct Haar handles of equal
+ * n, storage and stream; null or aliased pointers), HD_ERR_CAPACITY,
+ * HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_usv_step(hd_handle U, hd_handle V, const void* s, int32_t transpose,
+                const void* x, void* y);
+
 /* ------------------------------------------------------------------------
  * Checkpoint and resume.  The state of a handle after its last query is
  * what Algorithms 1 and 2 carry from one query to the next: the stored

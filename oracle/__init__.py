@@ -226,6 +226,16 @@ def goe_query(orc, x):
     return (orc.query(np.asarray(x, np.float64), True) + y_hat) / np.sqrt(2.0)
 
 
+def usv_query(orc_u, orc_v, s, x, transpose=False):
+    """Q = U diag(s) V with U, V independent lazy Haar matrices (section
+    "Other Random Matrix Ensembles", square case): Q x = U (s * (V x)),
+    Q' x = V' (s * (U' x))."""
+    x = np.asarray(x, np.float64)
+    if transpose:
+        return orc_v.query(s * orc_u.query(x, True), True)
+    return orc_u.query(s * orc_v.query(x, False), False)
+
+
 def replay(orc, xs, transposes):
     """Mode B: answer the given query vectors in order; returns the outputs."""
     return [orc.query(np.asarray(x, np.float64), bool(tr))

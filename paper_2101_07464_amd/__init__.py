@@ -437,3 +437,21 @@ class LazyGOE(LazyMatrix):
     def run(self, *args, **kwargs):
         raise TypeError("LazyGOE answers single queries (mv); the built-in "
                         "trajectories run on LazyMatrix")
+
+
+def usv_mv(U, V, s, x, transpose=False):
+    """y = Q x (or Q' x) for Q = U diag(s) V with U, V two Haar LazyMatrix
+    handles of the same n, dtype and device (``hd_usv_step``)."""
+    torch = _torch()
+    if U.device != V.device or U.dtype != V.dtype or U.n != V.n:
+        raise ValueError("U and V must match in n, dtype and device")
+    x = U._vec(x, U.n)
+    s = U._vec(s, U.n)
+    y = torch.empty(U.n, dtype=U.dtype, device=U.device)
+    U._sync_stream()
+    V._sync_stream()
+    _lib.check(_lib.load().hd_usv_step(
+        U._h, V._h, ctypes.c_void_p(s.data_ptr()), 1 if transpose else 0,
+        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
+        "hd_usv_step")
+    return y

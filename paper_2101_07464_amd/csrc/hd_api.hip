@@ -1239,6 +1239,31 @@ int hd_goe_step(hd_handle h, const void* x, void* y) {
   return query(h, 1, x, qtx, 0, f);
 }
 
+int hd_usv_step(hd_handle U, hd_handle V, const void* s, int32_t transpose,
+                const void* x, void* y) {
+  if (!U || !V || U == V || !s || !x || !y || x == y) return HD_ERR_INVALID;
+  if (transpose != 0 && transpose != 1) return HD_ERR_INVALID;
+  if (U->cfg.ensemble != HD_HAAR || V->cfg.ensemble != HD_HAAR ||
+      U->cfg.n != V->cfg.n || U->cfg.storage != V->cfg.storage ||
+      U->stream != V->stream)
+    return HD_ERR_INVALID;
+  // y = U (s .* (V x)), or y = V' (s .* (U' x)): the first handle's query
+  // forms s .* (its answer) in its epilogue, the second answers that
+  hd_ctx* first = transpose ? U : V;
+  hd_ctx* second = transpose ? V : U;
+  if (first->t >= first->cfg.t_max || second->t >= second->cfg.t_max)
+    return HD_ERR_CAPACITY;
+  int rc = ista_buffers(first);
+  if (rc) return rc;
+  DynFuse f = no_dyn();
+  f.kind = kDynScale;
+  f.x = s;
+  f.xnext = first->ista[1];
+  rc = query(first, transpose, x, first->ista[0], 0, f);
+  if (rc) return rc;
+  return query(second, transpose, first->ista[1], y, 0, no_dyn());
+}
+
 static int ista_room(const hd_ctx* h, int nq, int pq) {
   if ((int64_t)h->t + nq > h->cfg.t_max) return HD_ERR_CAPACITY;
   if (h->cfg.ensemble == HD_GINIBRE &&

@@ -102,7 +102,8 @@ enum DynKind {
   kDynNormalize = 3, // (unfused; see k_dyn)
   kDynResidual = 4,  // xnext = x - y                (x: the observation)
   kDynLista = 5,     // aux = v = x + a y; xnext = soft(v, b)
-  kDynAxpy = 6       // xnext = x - a y
+  kDynAxpy = 6,      // xnext = x - a y
+  kDynScale = 7      // xnext = x y (x: a diagonal, entrywise)
 };
 
 struct DynFuse {

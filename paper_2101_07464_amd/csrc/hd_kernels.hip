@@ -469,6 +469,8 @@ __device__ __forceinline__ double dyn_store(const DynFuse& d, int64_t i,
     const T v = (T)(x + d.a * y);  // v_t = x_t + a_t Q'(.)
     ((T*)d.aux)[i] = v;
     out = soft((double)v, d.b);
+  } else if (d.kind == kDynScale) {
+    out = x * y;  // a diagonal matrix times y
   } else {  // kDynAxpy
     out = x - d.a * y;
   }

@@ -301,6 +301,32 @@ def test_goe_entry_variances():
     assert abs(cols.mean(axis=0)).max() < 5 * sig * np.sqrt(2.0 / trials)
 
 
+def test_usv_exact_reconstruction_and_singular_values():
+    """Section "Other Random Matrix Ensembles", Q = U diag(s) V: every
+    answer (Q and Q' queries, mixed) equals that of U_rec diag(s) V_rec for
+    any completions of the two lazy Haar matrices, whose singular values
+    are |s|."""
+    n, K = 12, 6
+    rng = np.random.default_rng(8)
+    s = rng.standard_normal(n) * 2.0
+    ou = HDOracle(HAAR, n, seed=3, trial=1)
+    ov = HDOracle(HAAR, n, seed=3, trial=2)
+    hist = []
+    for k in range(K):
+        tr = bool(rng.random() < 0.5)
+        x = rng.standard_normal(n)
+        hist.append((tr, x, oracle.usv_query(ou, ov, s, x, tr)))
+    assert ou.counts()[0] == K and ov.counts()[0] == K
+    for _ in range(2):
+        Ur = _haar_rec(ou, n, K, haar_dense(n - K, rng))
+        Vr = _haar_rec(ov, n, K, haar_dense(n - K, rng))
+        Qr = Ur @ np.diag(s) @ Vr
+        for tr, x, y in hist:
+            assert np.allclose((Qr.T if tr else Qr) @ x, y, atol=1e-12)
+        sv = np.linalg.svd(Qr, compute_uv=False)
+        assert np.allclose(np.sort(sv), np.sort(np.abs(s)), atol=1e-12)
+
+
 # ------------------------------------------------------- isometry (P4) ---
 
 def test_haar_isometry_long_mixed():
