@@ -421,7 +421,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2",
                     choices=sorted(list(WORKLOADS) + ["c3", "c5", "goe"]))
-    ap.add_argument("--c5-trials", type=int, default=16)
+    ap.add_argument("--c5-trials", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -222,8 +222,9 @@ int hd_lista_backward(hd_handle h, int32_t L, const float* a,
  * `lengths`, a whole trajectory of k queries on a scratch handle of that
  * size (x_{t+1} = tanh(y_t) + 0.5 x_t; Haar: M_t = Q; Gaussian: sigma^2 =
  * 1/n, Q and Q' alternating) under each candidate shape, and installs the
- * fastest, process-wide, for the ensemble and storage type (replacing its
- * earlier entries).  A handle created afterwards uses, per panel, the entry
+ * fastest (the built-in shape unless another is at least 3% faster),
+ * process-wide, for the ensemble and storage type (replacing its earlier
+ * entries).  A handle created afterwards uses, per panel, the entry
  * whose length is nearest its own in ratio, if within a factor of 2, and
  * the built-in rule otherwise.  report: NULL or 3 * count doubles receiving
  * the mean microseconds per trajectory under 1, 2 and 4 chunks.  Not

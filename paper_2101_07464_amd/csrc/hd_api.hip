@@ -144,9 +144,18 @@ Shape shape_of(int64_t ld, int cpt) {
 // shape (the most workgroups, hence the largest partial-sum buffers).
 int g_force_cpt = 0;
 
+// The built-in rule's chunks per workgroup for a panel of `dim` rows.
+int dim_rule(int64_t dim) {
+  return dim < ((int64_t)1 << 18) ? 1 : (dim < ((int64_t)1 << 19) ? 2 : 4);
+}
+
+// A tuned shape replaces the built-in one only when at least this much
+// faster.
+constexpr double kTuneMargin = 0.03;
+
 Shape pick_shape(int ens, int f64, int64_t dim, int64_t ld) {
   if (g_force_cpt) return shape_of(ld, g_force_cpt);
-  int c = dim < ((int64_t)1 << 18) ? 1 : (dim < ((int64_t)1 << 19) ? 2 : 4);
+  int c = dim_rule(dim);
   const int t = tuned_cpt(ens, f64, dim);
   if (t) c = t;
   const int e = env_int("HD_CPT", 0);
@@ -1402,7 +1411,7 @@ int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
     if (!rc && (hipEventCreate(&e0) != hipSuccess ||
                 hipEventCreate(&e1) != hipSuccess))
       rc = hip_fail(hipGetLastError());
-    double best = 0.0;
+    double best = 0.0, rule_us = 0.0;
     int best_cpt = 1;
     for (int c = 0; c < 3 && !rc; ++c) {
       for (int s = 0; s < 2; ++s) h->sh[s] = shape_of(h->ld[s], cands[c]);
@@ -1422,6 +1431,7 @@ int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
         rc = hip_fail(hipGetLastError());
       const double us = 1e3 * ms / 3.0;
       if (report) report[3 * i + c] = us;
+      if (cands[c] == dim_rule(n)) rule_us = us;
       if (!rc && (c == 0 || us < best)) {
         best = us;
         best_cpt = cands[c];
@@ -1431,6 +1441,12 @@ int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
     if (e1) (void)hipEventDestroy(e1);
     hd_free(h);
     if (rc) return rc;
+    // keep the built-in shape unless another is clearly faster (ties are
+    // run-to-run noise, and the built-in shape keeps the fused prologues
+    // where the trajectory timed here does not exercise them all)
+    const int rule = dim_rule(n);
+    if (best_cpt != rule && best > (1.0 - kTuneMargin) * rule_us)
+      best_cpt = rule;
     table.push_back({n, best_cpt});
   }
   std::sort(table.begin(), table.end());

@@ -106,7 +106,9 @@ def test_autotune_installs_fastest_shape(clean_shapes, ens):
     chosen, times = rep[n]
     print("autotune %s n=%d: %s -> %d" % (ens, n, times, chosen))
     assert all(np.isfinite(v) and v > 0 for v in times.values())
-    assert chosen == min(times, key=times.get)
+    # the fastest shape, unless the built-in one (1 chunk here) is within 3%
+    best = min(times, key=times.get)
+    assert chosen == (best if times[best] < 0.97 * times[1] else 1)
     # nearest tuned length within a factor of 2, else the built-in rule;
     # other ensembles and storage types keep the built-in rule
     assert hd.shape_rule(E, n + 15000, torch.float32) == chosen
