@@ -204,6 +204,21 @@ def main_batch(args):
     elapsed = time.perf_counter() - t0
     if B.status() != 0:
         raise RuntimeError("device reported a non-finite reflector norm")
+    # the same runs replayed from a recorded HIP graph (one submission per
+    # run; recording needs a non-default stream)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        B.set_graph(True)
+        for _ in range(max(args.warmup, 1)):
+            B.run(x1, "tanh", C3["a"], C3["b"])
+        gs.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            B.run(x1, "tanh", C3["a"], C3["b"])
+        gs.synchronize()
+        elapsed_g = time.perf_counter() - t0
+    if B.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
     del B
     # plain: a sample of the same trials, one handle and hd_run each
     rs = np.random.default_rng(7).choice(len(trials), C3["plain_sample"],
@@ -242,6 +257,9 @@ def main_batch(args):
                                       "(hd_run), plan with the same kernels"
                                       % len(rs)},
         "batched_vs_plain": value / plain,
+        "hipgraph_replay": {"value": W * args.steps / elapsed_g,
+                            "unit": "elem-updates/s",
+                            "ms_per_step": elapsed_g / args.steps * 1e3},
     }
     print(json.dumps(out), flush=True)
 

@@ -300,6 +300,16 @@ int hd_batch_run(hd_batch b, const hd_dynamics* dyn, const void* const* x1,
 /* Synchronise and report the sticky device flag (as hd_status). */
 int hd_batch_status(hd_batch b);
 
+/* Replay mode for hd_batch_run (enable = 1): the first run with a given
+ * x_out mode (NULL or not) records its whole launch sequence into a HIP
+ * graph; every later run uploads its per-run pointers and map parameters
+ * (as always) and launches that graph, one submission for all trials and
+ * steps.  Requires a non-null stream (set at init or by
+ * hd_batch_set_stream) for the recording.  enable = 0 returns to direct
+ * launches (recorded graphs are kept for a later enable).
+ * Errors: HD_ERR_INVALID, HD_ERR_UNSUPPORTED (null stream). */
+int hd_batch_set_graph(hd_batch b, int32_t enable);
+
 /* Change the stream of later calls. */
 int hd_batch_set_stream(hd_batch b, void* stream);
 

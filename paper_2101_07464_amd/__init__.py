@@ -323,6 +323,15 @@ class HaarBatch:
     def status(self):
         return _lib.load().hd_batch_status(self._h)
 
+    def set_graph(self, enable=True):
+        """Replay runs from a recorded HIP graph (``hd_batch_set_graph``);
+        the current torch stream must not be the default stream."""
+        _lib.check(_lib.load().hd_batch_set_stream(
+            self._h, _stream_ptr(self.device)), "hd_batch_set_stream")
+        _lib.check(_lib.load().hd_batch_set_graph(self._h,
+                                                  1 if enable else 0),
+                   "hd_batch_set_graph")
+
 
 def _lista_function():
     torch = _torch()

@@ -36,7 +36,7 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_batch_set_stream", "hd_batch_free", "hd_lista_forward",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
-           "hd_usv_step"]
+           "hd_usv_step", "hd_batch_set_graph"]
 
 
 class HDConfig(ctypes.Structure):
@@ -112,6 +112,7 @@ def load():
         "hd_export": (i32, [vp, vp, P(ctypes.c_size_t)]),
         "hd_goe_step": (i32, [vp, vp, vp]),
         "hd_usv_step": (i32, [vp, vp, vp, i32, vp, vp]),
+        "hd_batch_set_graph": (i32, [vp, i32]),
         "hd_import": (i32, [P(HDConfig), vp, ctypes.c_size_t, P(vp)]),
     }
     for name, (res, args) in sig.items():

@@ -40,6 +40,11 @@ struct hd_batch_ctx {
   int* flag = nullptr;
   void* zeros = nullptr;
   std::vector<void*> allocs;
+  // HIP graphs of a run's launch sequence (without, with the x_{T+1} copy),
+  // captured on first use when enabled; every launch argument is fixed by
+  // the trial set, and what changes between runs lives in device buffers
+  bool use_graph = false;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -66,8 +71,15 @@ int bfail(hipError_t e) {
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
+int launch_run(hd_batch_ctx* b, bool copy_out);
+
 void release(hd_batch_ctx* b) {
   (void)hipStreamSynchronize(b->stream);
+  for (auto& e : b->exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
   for (void* p : b->allocs) (void)hipFree(p);
   b->allocs.clear();
 }
@@ -390,6 +402,49 @@ int hd_batch_run(hd_batch b, const hd_dynamics* dyn, const void* const* x1,
                         b->stream));
     BHIP(hipStreamSynchronize(b->stream));
   }
+  const int gi = x_out ? 1 : 0;
+  if (b->use_graph && b->exec[gi]) {
+    BHIP(hipGraphLaunch(b->exec[gi], b->stream));
+    return HD_OK;
+  }
+  if (b->use_graph) {
+    // record this run's launches once; they run from the graph below
+    BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_run(b, x_out != nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return bfail(ec);
+    const hipError_t ei = hipGraphInstantiate(&b->exec[gi], g, nullptr,
+                                              nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      b->exec[gi] = nullptr;
+      return bfail(ei);
+    }
+    BHIP(hipGraphLaunch(b->exec[gi], b->stream));
+    return HD_OK;
+  }
+  return launch_run(b, x_out != nullptr);
+}
+
+int hd_batch_set_graph(hd_batch b, int32_t enable) {
+  if (!b || (enable != 0 && enable != 1)) return HD_ERR_INVALID;
+  if (enable && !b->stream) return HD_ERR_UNSUPPORTED;
+  b->use_graph = enable != 0;
+  return HD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The launches of one run: x_1 in, every step, x_{T+1} out (when asked).
+int launch_run(hd_batch_ctx* b, bool copy_out) {
+  const int C = b->count;
   BLCHK(launch_copy_jobs(b->jobs, C, b->stream));
   const BatchMap map{b->blk_trial, b->blk_first_d};
   const int f64 = b->f64, cpt = b->cpt;
@@ -409,8 +464,8 @@ int hd_batch_run(hd_batch b, const hd_dynamics* dyn, const void* const* x1,
     BLCHK(launch_pass_batch(f64, cpt, nblk, kPassRandHaar, b->dev, map, st,
                             b->stream));
   }
-  if (x_out) BLCHK(launch_copy_jobs(b->jobs + C, C, b->stream));
+  if (copy_out) BLCHK(launch_copy_jobs(b->jobs + C, C, b->stream));
   return HD_OK;
 }
 
-}  // extern "C"
+}  // namespace

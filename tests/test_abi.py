@@ -65,6 +65,10 @@ def test_null_arguments():
     assert L.hd_status(None) == _lib.HD_ERR_INVALID
     assert L.hd_counts(None, None, None, None) == _lib.HD_ERR_INVALID
     assert L.hd_free(None) == _lib.HD_OK
+    assert L.hd_batch_set_graph(None, 1) == _lib.HD_ERR_INVALID
+    assert L.hd_goe_step(None, None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_usv_step(None, None, None, 0, None, None) == \
+        _lib.HD_ERR_INVALID
     assert L.hd_run(None, None, 0, None, None, None, None, None) == \
         _lib.HD_ERR_INVALID
 

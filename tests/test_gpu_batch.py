@@ -135,3 +135,37 @@ def test_full_batch_4096_sampled_and_invariants():
     assert worst_map < 1e-6
     assert worst_iso < 1e-5
     assert worst < 1e-4
+
+
+def test_graph_replays_match_direct_runs():
+    """hd_batch_set_graph: the first run records the launch sequence into a
+    HIP graph, later runs replay it.  Every replay (new inputs included,
+    with unrelated eager GPU work and synchronisations in between) must
+    equal a direct run bit for bit, in both output modes."""
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B = hd.HaarBatch(TRIALS, dtype=torch.float32, device=DEV)
+        D = hd.HaarBatch(TRIALS, dtype=torch.float32, device=DEV)
+        B.set_graph(True)
+        inputs_sets = [_x1(torch.float32)]
+        g = torch.Generator().manual_seed(5)
+        inputs_sets.append([torch.randn(n, generator=g).to(DEV) / np.sqrt(n)
+                            for n, T, _, _ in TRIALS])
+        for rep in range(4):
+            x1 = inputs_sets[rep % 2]
+            got = [t.clone() for t in B.run(x1, "tanh", 2.0, 0.0)]
+            want = D.run(x1, "tanh", 2.0, 0.0)
+            s.synchronize()
+            for a, b in zip(got, want):
+                assert torch.equal(a, b), rep
+            # unrelated eager work between replays
+            z = torch.randn(512, 512, device=DEV)
+            (z @ z).sum().item()
+        for rep in range(3):
+            x1 = inputs_sets[rep % 2]
+            X, Y = B.run(x1, "tanh", 2.0, 0.0, record=True)
+            Xd, Yd = D.run(x1, "tanh", 2.0, 0.0, record=True)
+            s.synchronize()
+            for a, b in zip(X + Y, Xd + Yd):
+                assert torch.equal(a, b), rep
+        assert B.status() == 0 and D.status() == 0
