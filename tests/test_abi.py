@@ -159,3 +159,20 @@ def test_export_import_null_arguments():
     # shorter than the header
     assert L.hd_import(ctypes.byref(_cfg()), b"HDSTATE1", 8,
                        ctypes.byref(h)) == _lib.HD_ERR_INVALID
+
+
+@pytest.mark.parametrize("trials,count", [
+    ([], 0),                       # empty batch
+    ([(10, 0, 0, 0)], 1),          # T = 0
+    ([(10, 11, 0, 0)], 1),         # T > n
+    ([(0, 1, 0, 0)], 1),           # n = 0
+    ([(100, 5, 0, 0), (3, 4, 0, 1)], 2),
+])
+def test_batch_init_rejects_invalid_trials(trials, count):
+    L = _lib.load()
+    arr = (_lib.HDBatchTrial * max(len(trials), 1))(
+        *[_lib.HDBatchTrial(*t) for t in trials])
+    h = ctypes.c_void_p()
+    rc = L.hd_batch_init(_lib.HD_F32, arr, count, None, ctypes.byref(h))
+    assert rc == _lib.HD_ERR_INVALID
+    assert not h.value

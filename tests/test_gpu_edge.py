@@ -75,3 +75,16 @@ def test_haar_run_tiny():
     Xo, Yo = oracle.run_trajectory(orc, x1.cpu().numpy(), T, "tanh", 1.0,
                                    0.5, "alt")
     assert relerr(X.cpu(), Xo) < 1e-12 and relerr(Y.cpu(), Yo) < 1e-12
+
+
+def test_run_zero_steps_is_identity():
+    """hd_run with T = 0: no query, x_{T+1} = x_1, counters unchanged."""
+    n = 1000
+    A = hd.LazyMatrix(hd.HAAR, n, t_max=4, seed=1, device=DEV)
+    x1 = torch.randn(n, device=DEV)
+    xo, _ = A.run(x1, 0, "tanh", 1.0, 0.5, record=False)
+    X, Y = A.run(x1, 0, "tanh", 1.0, 0.5, record=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xo, x1) and torch.equal(X[0], x1)
+    assert Y.shape == (0, n)
+    assert A.counts() == (0, 0, 0)
