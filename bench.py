@@ -13,9 +13,20 @@ roofline fraction are taken (events perturb the launch stream, so that pass
 is not timed).
 
 Workloads (--workload):
-  c2  (default) Ginibre n = m = 65536, sigma = 1/sqrt(n), T = 100, queries
+  c4  (default) the large single trial: Haar n = 1e7, T = 200, Q-queries,
+      FP32 panels and vectors (two panels of 8 GB), FP64 accumulation, norms
+      and T; x_1 ~ N(0, I/n).  Its specified map x_{t+1} = y/||y|| + 0.1 x is
+      switched off in the library, so x_{t+1} = tanh(y) + 0.1 x stands in
+      (the same passes and bytes).  The line also carries the error of the
+      first answers against the FP64 oracle (replaying the GPU's own query
+      vectors), the Haar invariants over all 200 answers, and -- unless
+      --no-extras -- the batched-vs-plain ratio of the batched workload and
+      the reverse-over-forward time of the differentiated one.
+  c2  Ginibre n = m = 65536, sigma = 1/sqrt(n), T = 100, queries
       Q, Q', Q, ...; x_{t+1} = soft(y_t, 0.1) + 0.3 x_{t-1}, x_1 ~ N(0, I),
       x_0 = 0; FP32 panels and vectors, FP64 accumulation, norms and T.
+      Its panels (at most 52 MB) stay in the 256 MB Infinity Cache, so its
+      roofline is flagged cache-resident.
   c1  Haar n = 1000, T = 20, FP64; x_{t+1} = tanh(y_t) + 0.5 x_t,
       x_1 ~ N(0, I/n).
   c3  4096 independent Haar trials, n log-uniform in [1e3, 1e5], T uniform
@@ -51,15 +62,31 @@ KIND_NAMES = {0: "panel TDOT (k_tdot)", 1: "data-side GEMV-N (k_pass)",
 WORKLOADS = {
     "c2": dict(name="ginibre_n65536_T100_alt_soft_fp32", ensemble="ginibre",
                n=65536, T=100, dyn="soft_hist", a=0.1, b=0.3, pattern="alt",
-               f64=False, x1_scale=1.0, dense=True),
+               f64=False, x1_scale=1.0, dense=True, modeb=100,
+               title="Gaussian n=m=65536, T=100, Q and Q' alternating, FP32",
+               dyn_text="x_{t+1} = soft(y_t, 0.1) + 0.3 x_{t-1}",
+               cache_resident="cache-resident: the panels (at most 52 MB) "
+                              "fit the 256 MB Infinity Cache, so this "
+                              "fraction of the HBM peak measures latency, "
+                              "not HBM bandwidth"),
     "c1": dict(name="haar_n1000_T20_tanh_fp64", ensemble="haar", n=1000,
                T=20, dyn="tanh", a=1.0, b=0.5, pattern="Q", f64=True,
-               x1_scale=None),
+               x1_scale=None, modeb=20,
+               title="Haar n=1000, T=20, Q-queries, FP64",
+               dyn_text="x_{t+1} = tanh(y_t) + 0.5 x_t",
+               cache_resident="cache-resident: the panels (320 KB) fit the "
+                              "L2, so this fraction measures launch "
+                              "latency"),
     # the large single trial; its normalising map is switched off in the
     # library, so tanh(y) + 0.1 x stands in (same passes, same bytes)
     "c4": dict(name="haar_n1e7_T200_tanh_fp32", ensemble="haar", n=10000000,
                T=200, dyn="tanh", a=1.0, b=0.1, pattern="Q", f64=False,
-               x1_scale=None),
+               x1_scale=None, modeb=8,
+               title="large single trial: Haar n=1e7, T=200, Q-queries, FP32 "
+                     "(map tanh(y)+0.1x standing in for y/||y||+0.1x)",
+               dyn_text="x_{t+1} = tanh(y_t) + 0.1 x_t (stand-in: the "
+                        "specified y_t/||y_t|| + 0.1 x_t is switched off in "
+                        "the library)"),
 }
 
 KERNEL_OF_KIND = {(0, "ginibre"): "k_tdot", (1, "ginibre"): "k_pass<data>",
@@ -139,6 +166,30 @@ def dense_direct(wl, x1, steps):
                       "products, same map, same storage type" % (n, n, T)}
 
 
+def host_facts():
+    """CPU model, logical CPUs and RAM of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    ram = int(line.split()[1]) * 1024
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "ram_bytes": ram}
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle (single-threaded C) on the same workload: whole
     trajectories while they fit the time budget, else the first queries of
@@ -164,13 +215,16 @@ def cpu_baseline(wl, budget_s=15.0):
             if time.perf_counter() - t0 > budget_s:
                 break
         trial += 1
+        del orc
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return dict(value=work / dt, unit="elem-updates/s", cores=1, kind="oracle",
-                sample="%d queries (%d trajectories started) of the same "
-                       "workload, FP64 C oracle, single thread, %.1f s"
-                       % (done, trial, dt))
+    out = dict(value=work / dt, unit="elem-updates/s", cores=1, kind="oracle",
+               sample="%d queries (%d trajectories started) of the same "
+                      "workload, FP64 C oracle (gcc -O3), single thread, "
+                      "%.1f s" % (done, trial, dt))
+    out.update(host_facts())
+    return out
 
 
 def batch_bytes(n, T, es=4):
@@ -182,7 +236,8 @@ def batch_bytes(n, T, es=4):
     return float(es * np.sum(3.0 * n * k + 8.0 * n))
 
 
-def main_batch(args):
+def run_batch(args, steps, warmup):
+    """The batched workload; returns its result object."""
     import torch
     import paper_2101_07464_amd as hd
     from paper_2101_07464_amd import inputs
@@ -194,11 +249,11 @@ def main_batch(args):
     W = float(sum(nominal_work(n, T) for n, T, _, _ in trials))
     by = sum(batch_bytes(n, T) for n, T, _, _ in trials)
     B = hd.HaarBatch(trials, dtype=torch.float32, device=dev)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         B.run(x1, "tanh", C3["a"], C3["b"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         B.run(x1, "tanh", C3["a"], C3["b"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -209,11 +264,11 @@ def main_batch(args):
     gs = torch.cuda.Stream()
     with torch.cuda.stream(gs):
         B.set_graph(True)
-        for _ in range(max(args.warmup, 1)):
+        for _ in range(max(warmup, 1)):
             B.run(x1, "tanh", C3["a"], C3["b"])
         gs.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             B.run(x1, "tanh", C3["a"], C3["b"])
         gs.synchronize()
         elapsed_g = time.perf_counter() - t0
@@ -235,12 +290,12 @@ def main_batch(args):
         Ws += nominal_work(n, T)
         del A
     plain = Ws / tp
-    value = W * args.steps / elapsed
-    gbs = by * args.steps / elapsed / 1e9
+    value = W * steps / elapsed
+    gbs = by * steps / elapsed / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "elem-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": C3["name"], "trials": len(trials),
@@ -257,11 +312,11 @@ def main_batch(args):
                                       "(hd_run), plan with the same kernels"
                                       % len(rs)},
         "batched_vs_plain": value / plain,
-        "hipgraph_replay": {"value": W * args.steps / elapsed_g,
+        "hipgraph_replay": {"value": W * steps / elapsed_g,
                             "unit": "elem-updates/s",
-                            "ms_per_step": elapsed_g / args.steps * 1e3},
+                            "ms_per_step": elapsed_g / steps * 1e3},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 C5 = dict(name="ista50_ginibre_n262144_m131072_fp32", n=262144, m=131072,
@@ -354,13 +409,14 @@ def main_goe(args):
     print(json.dumps(out), flush=True)
 
 
-def main_adjoint(args):
+def run_adjoint(args, steps, warmup, K):
+    """The differentiated workload with K trials per step; returns its
+    result object."""
     import torch
     import paper_2101_07464_amd as hd
     from paper_2101_07464_amd import inputs
     dev = "cuda:0"
     n, m, L = C5["n"], C5["m"], C5["L"]
-    K = args.c5_trials
     sig = 1.0 / np.sqrt(m)
     xs = [torch.from_numpy(inputs.sparse_target(n, 0.1, 2.0, seed=0,
                                                 trial=b)).to(dev, torch.float32)
@@ -383,15 +439,15 @@ def main_adjoint(args):
             A.lista_backward(a, th, U, V, 2.0 * (X[-1] - xs[b]))
 
     def timed(backward):
-        for i in range(args.warmup):
+        for i in range(warmup):
             trial(i % K, backward)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             for b in range(K):
                 trial(b, backward)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+        return (time.perf_counter() - t0) / steps
 
     t_fb = timed(True)
     t_f = timed(False)
@@ -401,7 +457,7 @@ def main_adjoint(args):
     W_f = K * nominal_work(n, 1 + 2 * L)
     out = {
         "metric": METRIC, "value": W_fb / t_fb, "unit": "elem-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": t_fb * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
@@ -413,7 +469,7 @@ def main_adjoint(args):
                          "queries_per_trial": 1 + 2 * L},
         "adjoint_time_over_forward": t_fb / t_f,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_calibration():
@@ -432,44 +488,70 @@ def copy_calibration():
           flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2",
-                    choices=sorted(list(WORKLOADS) + ["c3", "c5", "goe"]))
-    ap.add_argument("--c5-trials", type=int, default=256)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="run only the plain copy used to scale PMC bytes")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the built-in launch-shape rule instead of "
-                         "timing the candidate shapes first")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU "
-              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def single_trial_checks(hd, A, x1, wl, n_modeb):
+    """Accuracy of the timed configuration: one more trajectory (key (0, 0),
+    same launch shape) with every x_t and y_t recorded.  The FP64 oracle
+    answers the GPU's own first n_modeb query vectors (per-step replay), and
+    the whole trajectory is checked against what holds for any orthogonal Q
+    (||y_t|| = ||x_t|| and Y'Y = X'X) or, for the Gaussian ensemble, only
+    the replay is reported."""
+    import torch
+    import oracle
+    n, T = wl["n"], wl["T"]
+    A.reset(0, 0)
+    X, Y = A.run(x1, T, wl["dyn"], wl["a"], wl["b"], wl["pattern"])
+    torch.cuda.synchronize()
+    if A.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    out = {}
+    kb = min(n_modeb, T)
+    Xh = X[:kb].double().cpu().numpy()
+    Yh = Y[:kb].double().cpu().numpy()
+    ens = oracle.GINIBRE if wl["ensemble"] == "ginibre" else oracle.HAAR
+    sig = 1.0 / np.sqrt(n) if ens == oracle.GINIBRE else 1.0
+    orc = oracle.HDOracle(ens, n, tmax=kb, seed=0, trial=0, sigma=sig)
+    tr = [wl["pattern"] == "alt" and t % 2 == 1 for t in range(kb)]
+    Yo = oracle.replay(orc, Xh, tr)
+    del orc
+    err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+              for a, b in zip(Yh, Yo))
+    out["oracle_replay"] = {
+        "queries": kb, "max_rel_err": err,
+        "tolerance": 1e-11 if wl["f64"] else 1e-4,
+        "what": "max over the first %d answers of max|y_gpu - y_oracle| / "
+                "max|y_oracle|, the FP64 oracle answering the GPU's own "
+                "query vectors" % kb}
+    if wl["ensemble"] == "haar" and wl["pattern"] == "Q":
+        iso, G = 0.0, None
+        for r0 in range(0, T, 25):
+            xs = X[r0:min(r0 + 25, T)].double()
+            ys = Y[r0:min(r0 + 25, T)].double()
+            nx = torch.linalg.vector_norm(xs, dim=1)
+            ny = torch.linalg.vector_norm(ys, dim=1)
+            iso = max(iso, float(torch.max(torch.abs(ny / nx - 1.0))))
+        Xd = X[:T].double()
+        Gx = Xd @ Xd.T
+        del Xd
+        Yd = Y[:T].double()
+        Gy = Yd @ Yd.T
+        del Yd
+        gram = float(torch.max(torch.abs(Gy - Gx)) / torch.max(torch.abs(Gx)))
+        out["haar_invariants"] = {
+            "answers": T, "max_isometry_err": iso, "gram_rel_err": gram,
+            "what": "max_t | ||y_t|| / ||x_t|| - 1 | and max|Y'Y - X'X| / "
+                    "max|X'X| over every answer of the trajectory (both hold "
+                    "for any orthogonal Q)"}
+    del X, Y
+    torch.cuda.empty_cache()
+    return out
 
-    if args.workload == "c3":
-        main_batch(args)
-        return
-    if args.workload == "c5":
-        main_adjoint(args)
-        return
-    if args.workload == "goe":
-        main_goe(args)
-        return
 
+def run_single(args, wl):
+    """One of the single-trial workloads (c1, c2, c4); returns its line."""
     import torch
     import paper_2101_07464_amd as hd
     from paper_2101_07464_amd import inputs
 
-    wl = WORKLOADS[args.workload]
     n, T = wl["n"], wl["T"]
     dev = "cuda:0"
     dtype = torch.float64 if wl["f64"] else torch.float32
@@ -496,9 +578,10 @@ def main():
     elapsed = time.perf_counter() - t0
     if A.status() != 0:
         raise RuntimeError("device reported a non-finite reflector norm")
-    # Kernel durations: the same steps again with HIP events around every
-    # panel launch (on the library's stream).  Events add work between
-    # launches, so this pass is kept out of the timed region above.
+    # Kernel durations: the same steps again with HIP events recorded by the
+    # dispatches of every panel launch (on the library's stream).  Events
+    # add work between launches, so this pass is kept out of the timed
+    # region above.
     A.profile(True)
     for i in range(args.steps):
         step(i)
@@ -507,8 +590,8 @@ def main():
     A.profile(False)
     dom = max(kinds, key=lambda k: kinds[k][0])
     ms, launches, nbytes = kinds[dom]
-    traffic = measured_traffic(wl["name"],
-                               KERNEL_OF_KIND[(dom, wl["ensemble"])])
+    kname = KERNEL_OF_KIND[(dom, wl["ensemble"])]
+    traffic = measured_traffic(wl["name"], kname)
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     W = nominal_work(n, T)
     out = {
@@ -524,26 +607,127 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if wl["f64"] else "f32",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "n": n, "T": T,
+        "config": {"workload": wl["title"], "n": n, "T": T,
                    "ensemble": wl["ensemble"], "pattern": wl["pattern"],
-                   "dynamics": wl["dyn"],
+                   "dynamics": wl["dyn_text"],
                    "precision": ("FP64 panels and vectors" if wl["f64"] else
                                  "FP32 panels and vectors, FP64 accumulation,"
                                  " norms, signs and T"),
                    "elem_updates_per_step": W, "launch_shape": shape},
         "roofline": {"bound": "hbm", "kernel": KIND_NAMES[dom],
+                     "kernel_symbol": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "launches": launches,
+                     "traffic": traffic,
+                     "traffic_source": ("FETCH_SIZE + WRITE_SIZE per launch "
+                                        "from the committed rocprofv3 PMC "
+                                        "summary of these kernel sources "
+                                        "(profiles/)" if traffic else
+                                        "no PMC summary for these kernel "
+                                        "sources"),
+                     "launches": launches,
                      "avg_launch_us": ms * 1e3 / max(launches, 1),
-                     "algorithmic_bytes_per_launch": nbytes / max(launches, 1)},
+                     "algorithmic_bytes_per_launch":
+                         nbytes / max(launches, 1)},
     }
+    for k in (0, 1, 2):
+        kms, kl, kb = kinds[k]
+        if kl:
+            out["roofline"].setdefault("per_kernel", {})[
+                KERNEL_OF_KIND[(k, wl["ensemble"])]] = {
+                    "avg_launch_us": kms * 1e3 / kl,
+                    "frac": kb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if wl.get("cache_resident"):
+        out["roofline"]["residency"] = wl["cache_resident"]
+    if not args.no_checks:
+        out["accuracy"] = single_trial_checks(hd, A, x1, wl, wl["modeb"])
+    A.close()
+    del A
+    torch.cuda.empty_cache()
     if wl.get("dense", False):
         out["dense_direct"] = dense_direct(wl, x1, args.steps)
         out["vs_dense_direct"] = (out["dense_direct"]["ms_per_step"] /
                                   out["ms_per_step"])
+    return out
+
+
+def extras(args, out):
+    """The batched and the differentiated workloads, reduced to their
+    ratios against the plain per-trial launch and the forward-only run."""
+    t0 = time.perf_counter()
+    try:
+        b = run_batch(args, args.extra_steps, 1)
+        out["batched_vs_plain"] = b["batched_vs_plain"]
+        out["batched"] = {
+            "workload": b["config"]["workload"], "value": b["value"],
+            "unit": b["unit"], "ms_per_step": b["ms_per_step"],
+            "steps": b["steps"], "frac_hbm_whole_step": b["roofline"]["frac"],
+            "plain_per_trial": b["plain_per_trial"],
+            "hipgraph_replay_ms_per_step":
+                b["hipgraph_replay"]["ms_per_step"]}
+    except Exception as e:  # reported, not fatal for the headline line
+        out["batched_error"] = repr(e)
+    try:
+        a = run_adjoint(args, args.extra_steps, 1, args.extra_c5_trials)
+        out["adjoint_time_over_forward"] = a["adjoint_time_over_forward"]
+        out["adjoint"] = {
+            "workload": a["config"]["workload"], "value": a["value"],
+            "unit": a["unit"], "ms_per_step": a["ms_per_step"],
+            "trials_per_step": a["config"]["trials_per_step"],
+            "forward_only": a["forward_only"]}
+    except Exception as e:
+        out["adjoint_error"] = repr(e)
+    out["extras_wall_s"] = time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4",
+                    choices=sorted(list(WORKLOADS) + ["c3", "c5", "goe"]))
+    ap.add_argument("--c5-trials", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only the plain copy used to scale PMC bytes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the recorded trajectory checked against the "
+                         "oracle and the invariants")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c4 only: skip the batched and differentiated "
+                         "ratios")
+    ap.add_argument("--extra-steps", type=int, default=2)
+    ap.add_argument("--extra-c5-trials", type=int, default=64)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in launch-shape rule instead of "
+                         "timing the candidate shapes first")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "c3":
+        print(json.dumps(run_batch(args, args.steps, args.warmup)),
+              flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(run_adjoint(args, args.steps, args.warmup,
+                                     args.c5_trials)), flush=True)
+        return
+    if args.workload == "goe":
+        main_goe(args)
+        return
+    wl = WORKLOADS[args.workload]
+    out = run_single(args, wl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
+    if args.workload == "c4" and not args.no_extras:
+        extras(args, out)
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,8 @@
 """Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle_hd.so.
 
-Plain C11 with IEEE semantics (no fast-math, no -march) so the library built
-here runs on any x86-64 host.
+Plain C11 at -O3 with IEEE semantics (no fast-math, which would let the
+compiler reorder the floating-point sums; no -march, so the library built here
+runs on any x86-64 host).
 """
 import os
 import subprocess
@@ -13,7 +14,7 @@ LIB = os.path.join(HERE, "liboracle_hd.so")
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
            "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
