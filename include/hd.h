@@ -90,7 +90,9 @@ int hd_counts(hd_handle h, int32_t* t, int32_t* r, int32_t* l);
 
 /* Forget every revealed reflector and restart at t = 0 with a new key
  * (seed, trial), reusing the handle's device buffers: the next query is the
- * first query of a fresh, independent Q.  Stream-ordered; no allocation. */
+ * first query of a fresh, independent Q.  Also clears the sticky device flag
+ * (hd_status reports HD_OK again unless a later query sets it).
+ * Stream-ordered; no allocation.  Errors: HD_ERR_INVALID, HD_ERR_HIP. */
 int hd_reset(hd_handle h, uint32_t seed, uint32_t trial);
 
 /* Change the stream used by later calls (hipStream_t, NULL = null stream). */

@@ -838,26 +838,8 @@ int move_state(hd_ctx* h, const StateHeader& H, char* buf, bool to_host) {
   return rc;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* hd_strerror(int code) {
-  switch (code) {
-    case HD_OK: return "ok";
-    case HD_ERR_INVALID: return "invalid argument";
-    case HD_ERR_CAPACITY: return "capacity exhausted (t_max or min(m,n))";
-    case HD_ERR_NOMEM: return "device allocation failed";
-    case HD_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
-    case HD_ERR_NONFINITE: return "non-finite reflector norm";
-    case HD_ERR_UNSUPPORTED: return "unsupported configuration";
-    default: return "unknown error";
-  }
-}
-
-int hd_init(const hd_config* cfg, hd_handle* out) {
-  if (!cfg || !out) return HD_ERR_INVALID;
-  *out = nullptr;
+// Validation of a configuration (hd_init's rules).
+int check_config(const hd_config* cfg) {
   if (cfg->ensemble != HD_GINIBRE && cfg->ensemble != HD_HAAR)
     return HD_ERR_INVALID;
   if (cfg->storage != HD_F32 && cfg->storage != HD_F64) return HD_ERR_INVALID;
@@ -868,9 +850,12 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   if (cfg->ensemble == HD_GINIBRE && !(cfg->sigma > 0.0))
     return HD_ERR_INVALID;
   if (cfg->n > ((int64_t)1 << 40)) return HD_ERR_NOMEM;
+  return HD_OK;
+}
 
-  hd_ctx* h = new (std::nothrow) hd_ctx();
-  if (!h) return HD_ERR_NOMEM;
+// Sizes, launch shapes and device buffers of a handle (zeroed by dalloc, or
+// left for the caller to clear when carved).
+int init_layout(hd_ctx* h, const hd_config* cfg) {
   h->cfg = *cfg;
   h->stream = (hipStream_t)cfg->stream;
   h->f64 = cfg->storage == HD_F64;
@@ -889,14 +874,10 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
     if (h->sh[s].nwg > maxwg) maxwg = h->sh[s].nwg;
   }
   int rc = HD_OK;
-#define ALLOC(ptr, bytes)                                   \
-  do {                                                      \
-    rc = dalloc(h, &(ptr), (bytes));                        \
-    if (rc != HD_OK) {                                      \
-      free_all(h);                                          \
-      delete h;                                             \
-      return rc;                                            \
-    }                                                       \
+#define ALLOC(ptr, bytes)              \
+  do {                                 \
+    rc = dalloc(h, &(ptr), (bytes));   \
+    if (rc != HD_OK) return rc;        \
   } while (0)
   for (int s = 0; s < 2; ++s) {
     PanelDev& P = h->P[s];
@@ -930,20 +911,51 @@ int hd_init(const hd_config* cfg, hd_handle* out) {
   }
   ALLOC(h->flag, sizeof(int) * 4);
 #undef ALLOC
+  return HD_OK;
+}
+
+// The non-zero initial values: pi[0] = 1 on both sides, sigma.
+int init_values(hd_ctx* h) {
   for (int s = 0; s < 3; ++s) {
     double* p = s < 2 ? h->P[s].pi : h->gscal + 1;
-    const double v = s < 2 ? 1.0 : cfg->sigma;
-    if (launch_fill(p, v, 1, h->stream) != 0) {
-      free_all(h);
-      delete h;
-      return HD_ERR_HIP;
-    }
+    const double v = s < 2 ? 1.0 : h->cfg.sigma;
+    if (launch_fill(p, v, 1, h->stream) != 0) return HD_ERR_HIP;
   }
-  if (hipStreamSynchronize(h->stream) != hipSuccess) {
-    int e = hip_fail(hipGetLastError());
+  return HD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hd_strerror(int code) {
+  switch (code) {
+    case HD_OK: return "ok";
+    case HD_ERR_INVALID: return "invalid argument";
+    case HD_ERR_CAPACITY: return "capacity exhausted (t_max or min(m,n))";
+    case HD_ERR_NOMEM: return "device allocation failed";
+    case HD_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case HD_ERR_NONFINITE: return "non-finite reflector norm";
+    case HD_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+int hd_init(const hd_config* cfg, hd_handle* out) {
+  if (!cfg || !out) return HD_ERR_INVALID;
+  *out = nullptr;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  hd_ctx* h = new (std::nothrow) hd_ctx();
+  if (!h) return HD_ERR_NOMEM;
+  rc = init_layout(h, cfg);
+  if (!rc) rc = init_values(h);
+  if (!rc && hipStreamSynchronize(h->stream) != hipSuccess)
+    rc = hip_fail(hipGetLastError());
+  if (rc) {
     free_all(h);
     delete h;
-    return e;
+    return rc;
   }
   *out = h;
   return HD_OK;
@@ -960,7 +972,9 @@ int hd_reset(hd_handle h, uint32_t seed, uint32_t trial) {
   if (!h) return HD_ERR_INVALID;
   // Panel entries above each column's diagonal are never written, so they
   // are still zero; every other entry a query reads is rewritten before it
-  // is read.  Only the host-side counters and the key change.
+  // is read.  The host-side counters and the key change, and the sticky
+  // device flag is cleared (stream-ordered) for the fresh matrix.
+  LCHK(launch_zero(h->flag, sizeof(int) * 4, h->stream));
   h->cfg.seed = seed;
   h->cfg.trial = trial;
   h->t = h->r = h->l = 0;

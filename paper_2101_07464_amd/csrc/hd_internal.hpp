@@ -358,5 +358,7 @@ inline int lista_blocks(int64_t n) {
 int launch_lista_adj(int f64, const ListaAdjArgs& a, double* ga, double* gt,
                      hipStream_t s);
 int launch_fill(double* p, double v, int64_t count, hipStream_t s);
+// Zero `bytes` (a multiple of 4) at p.
+int launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace hd

@@ -337,6 +337,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
       upG = (double)(T)(gk + sG * nuG);
       tauG = 2.0 / (ssG + upG * upG);
     }
+    if (!isfinite(nuG) || !isfinite(tauG)) a.flag[0] = 1;
     VG[(int64_t)k * ldG + k] = (T)upG;
     a.G.tau[k] = tauG;
     a.G.nu[k] = nuG;
@@ -1092,6 +1093,14 @@ __global__ __launch_bounds__(kWG) void k_dyn(DynArgs a) {
   }
 }
 
+// Zero `words` 4-byte words (a fill kernel rather than a memset node, so
+// that the clearing can sit in a captured HIP graph).
+__global__ __launch_bounds__(kWG) void k_zero(uint32_t* p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * kWG)
+    p[i] = 0u;
+}
+
 __global__ __launch_bounds__(kWG) void k_fill(double* p, double v,
                                               int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < count;
@@ -1369,6 +1378,17 @@ int launch_dyn(int f64, const DynArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dyn<float>), dim3((int)blocks),
                        dim3(kWG), 0, s, a);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words <= 0) return 0;
+  int64_t blocks = (words + kWG - 1) / kWG;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_zero, dim3((int)blocks), dim3(kWG), 0, s,
+                     (uint32_t*)p, words);
   HD_CHECK_LAUNCH();
   return 0;
 }
