@@ -82,14 +82,16 @@ def test_c2_like_alternating_trajectory(dtype, tol):
     else:
         # These dynamics amplify storage rounding: the oracle itself with its
         # state rounded to FP32 drifts from its FP64 run.  The GPU's free run
-        # must stay within 10x of that intrinsic drift (and within the 1e-4
-        # bound while the drift is below it).
+        # (which also rounds its stored reflectors to FP32) must stay within
+        # 3x of that intrinsic drift over the trajectory and 6x per step (and
+        # within the 1e-4 bound while the drift is below it).
         orc_c = oracle.HDOracle(oracle.GINIBRE, n, tmax=T, seed=0, sigma=sig)
         Xc, _ = oracle.run_trajectory(orc_c, X[0], T, "soft_hist", 0.1, 0.3,
                                       "alt", state_dtype=np.float32)
         drift = [relerr(xc, xo) for xc, xo in zip(Xc, Xo)]
+        assert max(ea) <= max(tol, 3 * max(drift))
         for t, (e, d) in enumerate(zip(ea, drift)):
-            assert e <= max(tol, 10 * d), (t, e, d)
+            assert e <= max(tol, 6 * d), (t, e, d)
 
 
 @pytest.mark.parametrize("m,n", [(3001, 2200), (1500, 4097)])

@@ -149,9 +149,12 @@ def test_gaussian_n65536_T100_alternating_full_size(clean_shapes):
     print("gaussian n=65536 T=100: mode B max %.2e" % max(err))
     assert max(err) < 1e-4
     # Mode A: the free-running trajectory against the oracle's FP64 run,
-    # within 10x the drift the oracle itself shows with its state rounded to
-    # FP32 (these dynamics amplify storage rounding), and within 1e-4 while
-    # that drift is below it
+    # measured against the drift the oracle itself shows with its state
+    # rounded to FP32 (these dynamics amplify storage rounding).  The GPU
+    # also rounds every stored reflector to FP32, so it injects somewhat
+    # more error per step than that state-only run: the whole trajectory
+    # must stay within 3x the oracle's largest drift, and every step within
+    # 6x that step's drift (or 1e-4 while the drift is below it)
     orc = oracle.HDOracle(oracle.GINIBRE, n, tmax=T, seed=0, sigma=sig)
     Xo, _ = oracle.run_trajectory(orc, X[0], T, "soft_hist", 0.1, 0.3, "alt")
     orc_c = oracle.HDOracle(oracle.GINIBRE, n, tmax=T, seed=0, sigma=sig)
@@ -161,8 +164,11 @@ def test_gaussian_n65536_T100_alternating_full_size(clean_shapes):
     drift = [relerr(xc, xo) for xc, xo in zip(Xc, Xo)]
     print("gaussian n=65536 T=100: mode A max %.2e (FP32-state oracle "
           "drift max %.2e)" % (max(ea), max(drift)))
+    ratio = max(e / max(d, 1e-4 / 6) for e, d in zip(ea, drift))
+    print("  largest per-step ratio to the drift %.2f" % ratio)
+    assert max(ea) <= 3 * max(drift)
     for t, (e, d) in enumerate(zip(ea, drift)):
-        assert e <= max(1e-4, 10 * d), (t, e, d)
+        assert e <= max(1e-4, 6 * d), (t, e, d)
 
 
 def test_haar_n1e7_T200_full_size(clean_shapes):

@@ -496,3 +496,37 @@ def test_forced_sign_changes_basis_not_law():
     Hb = reflector_matrix(n, b.reflector(SIDE_R, 1))
     assert np.allclose(Hb @ x, np.linalg.norm(x) * np.eye(n)[0], atol=1e-13)
     assert np.isclose(np.linalg.norm(yb), np.linalg.norm(x), rtol=1e-13)
+
+
+def test_normalising_map_properties():
+    """The map of the large single trial, x_{t+1} = y/||y|| + b x_t
+    (eq. (dynamics) with f_t a normalisation plus a memory term): with
+    b = 0 the output has unit norm; it is invariant to positive scalings of
+    y; and f - b x_t is a positive multiple of y (so neither x_{t-1} nor a
+    wrong power of ||y|| enters)."""
+    rng = np.random.default_rng(17)
+    f = oracle.f_normalize
+    for n in (1, 5, 1000):
+        y = rng.standard_normal(n) * 3.7
+        xt = rng.standard_normal(n)
+        xp = rng.standard_normal(n)
+        assert abs(np.linalg.norm(f(y, xt, xp, 0.0, 0.0)) - 1.0) < 1e-14
+        assert np.allclose(f(y, xt, xp, 0.0, 0.1),
+                           f(123.5 * y, xt, xp, 0.0, 0.1), atol=1e-14)
+        d = f(y, xt, xp, 0.0, 0.1) - 0.1 * xt
+        c = float(d @ y) / float(y @ y)
+        assert c > 0 and np.allclose(d, c * y, atol=1e-14)
+
+
+def test_normalising_trajectory_on_haar_keeps_unit_norm():
+    """Along a Haar trajectory with Q-queries only and b = 0, every state
+    after the first has unit norm (the lazy Q is an isometry, Theorem 2,
+    and the map normalises its answer): ||x_{t+1}|| = 1 and
+    ||y_t|| = ||x_t||."""
+    n, T = 300, 25
+    orc = HDOracle(HAAR, n, seed=8)
+    x1 = np.random.default_rng(3).standard_normal(n) * 5.0
+    X, Y = oracle.run_trajectory(orc, x1, T, "normalize", 0.0, 0.0)
+    assert np.allclose(np.linalg.norm(X[1:], axis=1), 1.0, atol=1e-13)
+    assert np.allclose(np.linalg.norm(Y, axis=1),
+                       np.linalg.norm(X[:-1], axis=1), rtol=1e-13)
