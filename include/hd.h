@@ -41,7 +41,8 @@ enum {
   HD_ERR_NOMEM = -3,     /* device allocation failed */
   HD_ERR_HIP = -4,       /* a HIP runtime call failed */
   HD_ERR_NONFINITE = -5, /* a reflector norm was NaN/Inf (sticky) */
-  HD_ERR_UNSUPPORTED = -6
+  HD_ERR_UNSUPPORTED = -6,
+  HD_ERR_TOO_LARGE = -7  /* beyond the allocation-free entry point's scratch */
 };
 
 enum { HD_GINIBRE = 0, HD_HAAR = 1 };
@@ -183,6 +184,34 @@ typedef struct {
  * Errors as hd_step; on HD_ERR_CAPACITY nothing is launched. */
 int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
            const void* x0, void* x_out, void* traj_x, void* traj_y);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free trajectory, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).
+ *
+ * hd_run_noalloc(cfg, ...) does what hd_init(cfg) + hd_run(...) + hd_free
+ * would do -- a fresh Q with the key (cfg->seed, cfg->trial), T steps of the
+ * built-in dynamics, the same kernels and launch shapes, hence the same
+ * results -- but every device buffer the library needs (panels, FP64
+ * scalars, partial sums, hd_run's internal x ring, y and zero vectors) lives
+ * in one static device array of HD_NOALLOC_SCRATCH_BYTES per GPU, which each
+ * GPU the library runs on holds until the process ends.  The call performs
+ * no hipMalloc, hipFree or other allocating routine and no synchronisation;
+ * it clears the region with a fill kernel on cfg->stream and launches the
+ * trajectory there.  The caller still owns x1, x0, x_out, traj_x and traj_y
+ * (as for hd_run; requires m == n).  Every call on a GPU shares that GPU's
+ * array, whose contents are the last call's: calls that overlap on one GPU
+ * (different streams, or host threads) race and must be serialised by the
+ * caller.  hd_noalloc_scratch_bytes reports the bytes cfg needs.
+ * Errors: HD_ERR_INVALID (bad cfg or arguments, m != n),
+ * HD_ERR_TOO_LARGE (the layout exceeds the array), HD_ERR_UNSUPPORTED
+ * (as hd_run's maps and patterns), HD_ERR_CAPACITY, HD_ERR_HIP. */
+#define HD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int hd_noalloc_scratch_bytes(const hd_config* cfg, size_t* bytes);
+int hd_run_noalloc(const hd_config* cfg, const hd_dynamics* dyn, int32_t T,
+                   const void* x1, const void* x0, void* x_out, void* traj_x,
+                   void* traj_y);
 
 /* ------------------------------------------------------------------------
  * Unrolled ISTA with learned per-layer parameters, and its gradient.

@@ -17,6 +17,8 @@ HD_ERR_NOMEM = -3
 HD_ERR_HIP = -4
 HD_ERR_NONFINITE = -5
 HD_ERR_UNSUPPORTED = -6
+HD_ERR_TOO_LARGE = -7
+HD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 HD_GINIBRE = 0
 HD_HAAR = 1
@@ -36,7 +38,8 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_batch_set_stream", "hd_batch_free", "hd_lista_forward",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
-           "hd_usv_step", "hd_batch_set_graph"]
+           "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
+           "hd_noalloc_scratch_bytes"]
 
 
 class HDConfig(ctypes.Structure):
@@ -114,6 +117,10 @@ def load():
         "hd_usv_step": (i32, [vp, vp, vp, i32, vp, vp]),
         "hd_batch_set_graph": (i32, [vp, i32]),
         "hd_import": (i32, [P(HDConfig), vp, ctypes.c_size_t, P(vp)]),
+        "hd_run_noalloc": (i32, [P(HDConfig), P(HDDynamics), i32, vp, vp,
+                                 vp, vp, vp]),
+        "hd_noalloc_scratch_bytes": (i32, [P(HDConfig),
+                                           P(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -72,6 +73,14 @@ struct hd_ctx {
   void* ista[6];   // unrolled-ISTA work vectors (max(m, n) entries each)
   double* ista_part;
   int t, r, l;
+  // Buffers carved from a caller-independent static region instead of
+  // hipMalloc (the allocation-free entry point): base, used and capacity in
+  // bytes.  base == nullptr with active set only measures the layout.
+  struct {
+    int active;
+    char* base;
+    size_t used, cap;
+  } carve;
   std::vector<void*> allocs;
   // profiling
   int prof;
@@ -167,6 +176,15 @@ template <typename P>
 int dalloc(hd_ctx* h, P** out, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
+  if (h->carve.active) {
+    // 256-byte aligned slices of the static region, cleared together by the
+    // caller once the layout is complete
+    const size_t at = (h->carve.used + 255) / 256 * 256;
+    if (at + bytes > h->carve.cap) return HD_ERR_NOMEM;
+    h->carve.used = at + bytes;
+    *out = (P*)(h->carve.base ? h->carve.base + at : nullptr);
+    return HD_OK;
+  }
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return HD_ERR_NOMEM;
@@ -937,6 +955,9 @@ const char* hd_strerror(int code) {
     case HD_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
     case HD_ERR_NONFINITE: return "non-finite reflector norm";
     case HD_ERR_UNSUPPORTED: return "unsupported configuration";
+    case HD_ERR_TOO_LARGE:
+      return "problem exceeds the static scratch of the allocation-free "
+             "entry point";
     default: return "unknown error";
   }
 }
@@ -1481,6 +1502,104 @@ int hd_autotune_clear(void) {
   for (auto& e : g_tuned)
     for (auto& t : e) t.clear();
   return HD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free run --
+//
+// hd_run_noalloc carries a whole handle (panels, FP64 scalars, partial-sum
+// rows, trajectory vectors) in one file-scope device array per GPU instead of
+// hipMalloc'd buffers.  The array is reached through the address
+// hipGetSymbolAddress reports for the current device (the array's name is
+// only a host-side stand-in in host code).
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)HD_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device, looked up once per
+// device.
+int scratch_base(void** out) {
+  int dev = -1;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return HD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return HD_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HD_OK;
+}
+
+// Lays out a handle for cfg plus hd_run's internal vectors (a ring of three
+// x_t, y_t and the zero x_0) in the carve region of h.
+int noalloc_layout(hd_ctx* h, const hd_config* cfg) {
+  int rc = init_layout(h, cfg);
+  if (rc) return rc;
+  const size_t vb = (size_t)h->es * (size_t)cfg->n;
+  for (int i = 0; i < 3 && !rc; ++i) rc = dalloc(h, &h->ring[i], vb);
+  if (!rc) rc = dalloc(h, &h->ybuf, vb);
+  if (!rc) rc = dalloc(h, &h->zeros, vb);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hd_noalloc_scratch_bytes(const hd_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return HD_ERR_INVALID;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  hd_ctx h{};
+  h.carve.active = 1;
+  h.carve.base = nullptr;
+  h.carve.used = 0;
+  h.carve.cap = ~(size_t)0;
+  rc = noalloc_layout(&h, cfg);
+  if (rc) return rc;
+  *bytes = h.carve.used;
+  return HD_OK;
+}
+
+int hd_run_noalloc(const hd_config* cfg, const hd_dynamics* dyn, int32_t T,
+                   const void* x1, const void* x0, void* x_out, void* traj_x,
+                   void* traj_y) {
+  if (!cfg || !dyn || !x1 || T < 0) return HD_ERR_INVALID;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (cfg->m != cfg->n) return HD_ERR_INVALID;
+  size_t need = 0;
+  rc = hd_noalloc_scratch_bytes(cfg, &need);
+  if (rc) return rc;
+  if (need > kScratchBytes) return HD_ERR_TOO_LARGE;
+  void* base = nullptr;
+  rc = scratch_base(&base);
+  if (rc) return rc;
+  hd_ctx h{};
+  h.carve.active = 1;
+  h.carve.base = (char*)base;
+  h.carve.used = 0;
+  h.carve.cap = kScratchBytes;
+  rc = noalloc_layout(&h, cfg);
+  if (rc) return rc == HD_ERR_NOMEM ? HD_ERR_TOO_LARGE : rc;
+  // every call starts from a cleared region: the panels' rows above each
+  // column's diagonal and beyond n must be zero, and the previous call's
+  // contents are still there
+  LCHK(launch_zero(base, (h.carve.used + 3) / 4 * 4, h.stream));
+  rc = init_values(&h);
+  if (rc) return rc;
+  return hd_run(&h, dyn, T, x1, x0, x_out, traj_x, traj_y);
 }
 
 int hd_profile(hd_handle h, int32_t enable) {

@@ -29,7 +29,7 @@ def test_library_exports_every_symbol():
 
 
 def test_error_strings():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert _lib.strerror(code)
 
 
@@ -176,3 +176,30 @@ def test_batch_init_rejects_invalid_trials(trials, count):
     rc = L.hd_batch_init(_lib.HD_F32, arr, count, None, ctypes.byref(h))
     assert rc == _lib.HD_ERR_INVALID
     assert not h.value
+
+
+def test_noalloc_sizing_and_limit():
+    """The allocation-free entry point sizes its layout on the host and
+    refuses problems beyond its static array before touching the device."""
+    L = _lib.load()
+    need = ctypes.c_size_t()
+    assert L.hd_noalloc_scratch_bytes(ctypes.byref(_cfg(n=1000, m=1000,
+                                                         t_max=20)),
+                                      ctypes.byref(need)) == _lib.HD_OK
+    # two FP32 panels of 1024 x 20 plus vectors: well inside the array
+    assert 2 * 1024 * 20 * 4 < need.value < _lib.HD_NOALLOC_SCRATCH_BYTES
+    big = _cfg(n=1 << 20, m=1 << 20, t_max=64)
+    assert L.hd_noalloc_scratch_bytes(ctypes.byref(big),
+                                      ctypes.byref(need)) == _lib.HD_OK
+    assert need.value > _lib.HD_NOALLOC_SCRATCH_BYTES
+    dyn = _lib.HDDynamics(_lib.HD_DYN_TANH, _lib.HD_PATTERN_Q, 1.0, 0.5)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: refused first
+    assert L.hd_run_noalloc(ctypes.byref(big), ctypes.byref(dyn), 4, fake,
+                            None, None, None, None) == _lib.HD_ERR_TOO_LARGE
+    assert L.hd_run_noalloc(None, ctypes.byref(dyn), 4, fake, None, None,
+                            None, None) == _lib.HD_ERR_INVALID
+    assert L.hd_run_noalloc(ctypes.byref(_cfg(t_max=0)), ctypes.byref(dyn),
+                            4, fake, None, None, None,
+                            None) == _lib.HD_ERR_INVALID
+    assert L.hd_noalloc_scratch_bytes(None, ctypes.byref(need)) == \
+        _lib.HD_ERR_INVALID
