@@ -472,6 +472,89 @@ def run_adjoint(args, steps, warmup, K):
     return out
 
 
+SPECTRAL = dict(name="spectral_n1e5_m2e5_K50_fp32", n=100_000, m=200_000,
+                K=50)
+
+
+def main_spectral(args):
+    """Spectral method of Sec. 2.2: A = [I_n 0] Q, Q Haar of size
+    m = 2n, measurements y = tanh|A' xi|, K power steps of m D (eq. (D_mtx))
+    through the lazy Q (1 + 2K queries); a step is one whole run from a fresh
+    Q (hd_reset) to x_{K+1}."""
+    import torch
+    import oracle
+    import paper_2101_07464_amd as hd
+    dev = "cuda:0"
+    n, m, K = SPECTRAL["n"], SPECTRAL["m"], SPECTRAL["K"]
+    rng = np.random.default_rng(0)
+    xi_h = rng.standard_normal(n).astype(np.float32)
+    x1_h = rng.standard_normal(n).astype(np.float32)
+    xi = torch.from_numpy(xi_h).to(dev)
+    x1 = torch.from_numpy(x1_h).to(dev)
+    shape = tune_shapes(args, hd, hd.HAAR, [m], torch.float32, 32)
+    A = hd.LazyMatrix(hd.HAAR, m, t_max=1 + 2 * K, seed=0, device=dev)
+
+    def step(i):
+        A.reset(0, i)
+        return A.spectral_power(xi, x1, K)
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if A.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    A.profile(True)
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    kinds = {k: A.profile_read(k) for k in (0, 1, 2)}
+    A.profile(False)
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, launches, nbytes = kinds[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    W = nominal_work(m, 1 + 2 * K)
+    out = {
+        "metric": METRIC, "value": W * args.steps / elapsed,
+        "unit": "elem-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": SPECTRAL["name"], "n": n, "m": m,
+                   "power_steps": K, "queries": 1 + 2 * K,
+                   "elem_updates_per_step": W, "launch_shape": shape},
+        "roofline": {"bound": "hbm", "kernel": KIND_NAMES[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": launches,
+                     "avg_launch_us": ms * 1e3 / max(launches, 1),
+                     "residency": "panels of at most 2 x 80 MB: largely "
+                                  "cache-resident (256 MB Infinity Cache)"},
+    }
+    if not args.no_checks:
+        z, X = step(0)
+        torch.cuda.synchronize()
+        orc = oracle.HDOracle(oracle.HAAR, m, tmax=1 + 2 * K, seed=0, trial=0)
+        zo, Xo = oracle.spectral_power(orc, xi_h.astype(np.float64),
+                                       x1_h.astype(np.float64), K)
+        X = X.double().cpu().numpy()
+        err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+                  for a, b in zip(X, Xo))
+        rq = [float(X[k] @ X[k + 1] / (X[k] @ X[k])) for k in range(K)]
+        c = float(abs(X[-1] @ xi_h) / np.linalg.norm(X[-1]) /
+                  np.linalg.norm(xi_h))
+        out["accuracy"] = {"max_rel_err_vs_oracle": err, "tolerance": 1e-4,
+                           "what": "every iterate x_1..x_%d against the FP64 "
+                                   "oracle's own run" % (K + 1),
+                           "rayleigh_last": rq[-1],
+                           "cosine_with_signal": c}
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of known size (read 1 GiB, write 1 GiB, five
     times) for scaling the PMC byte counters of the panel kernels."""
@@ -686,7 +769,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4",
-                    choices=sorted(list(WORKLOADS) + ["c3", "c5", "goe"]))
+                    choices=sorted(list(WORKLOADS) +
+                                   ["c3", "c5", "goe", "spectral"]))
     ap.add_argument("--c5-trials", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
@@ -721,6 +805,9 @@ def main():
         return
     if args.workload == "goe":
         main_goe(args)
+        return
+    if args.workload == "spectral":
+        main_spectral(args)
         return
     wl = WORKLOADS[args.workload]
     out = run_single(args, wl)

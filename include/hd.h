@@ -101,29 +101,48 @@ int hd_set_stream(hd_handle h, void* stream);
 
 /* ------------------------------------------------------------------------
  * Gaussian orthogonal ensemble from the Gaussian one (section "Other Random
- * Matrix Ensembles"): for Q with i.i.d. N(0, s^2) entries, (Q + Q')/sqrt(2)
- * is GOE of scale s (diagonal N(0, 2 s^2), off-diagonal N(0, s^2)).
- * hd_goe_step answers y = Q x + Q' x with two queries on a square Gaussian
- * handle (Q x first, then Q' x with the sum formed in its epilogue), so a
- * handle created with sigma = s / sqrt(2) answers y = G x for G ~ s GOE(n),
- * the paper's y = (Q' x + Q x) / sqrt(2) for the scale-s Q.  Each call uses
- * two of the handle's t_max queries (one reflector per side).  x, y: device
- * vectors of n entries (storage type), not aliased.  Errors: HD_ERR_INVALID
- * (not a square Gaussian handle, null or aliased pointers),
+ * Matrix Ensembles"): for Q with i.i.d. N(0, s^2) entries,
+ * G = (Q + Q')/sqrt(2) is GOE of scale s (diagonal N(0, 2 s^2),
+ * off-diagonal N(0, s^2)).  hd_goe_step answers y = G x = (Q x + Q' x)/sqrt(2)
+ * with two queries on a square Gaussian handle of sigma = s (Q x first, then
+ * Q' x with the sum and the 1/sqrt(2) formed in its epilogue).  Each call
+ * uses two of the handle's t_max queries (one reflector per side).  x, y:
+ * device vectors of n entries (storage type), not aliased.  Errors:
+ * HD_ERR_INVALID (not a square Gaussian handle, null or aliased pointers),
  * HD_ERR_CAPACITY, HD_ERR_NOMEM, HD_ERR_HIP. */
 int hd_goe_step(hd_handle h, const void* x, void* y);
 
-/* Q = U S V with U, V independent Haar-orthogonal (two Haar handles of the
- * same n, storage type and stream) and S = diag(s) (section "Other Random
- * Matrix Ensembles", square case): transpose = 0 answers y = U (s .* (V x)),
- * transpose = 1 answers y = Q' x = V' (s .* (U' x)); one query on each
- * handle, the entrywise product formed in the first query's epilogue.
- * s, x, y: device vectors of n entries (storage type); x and y not
- * aliased.  Errors: HD_ERR_INVALID (not two distinct Haar handles of equal
- * n, storage and stream; null or aliased pointers), HD_ERR_CAPACITY,
- * HD_ERR_NOMEM, HD_ERR_HIP. */
+/* Q = U S V (section "Other Random Matrix Ensembles") with U ~ Haar(m) and
+ * V ~ Haar(n) independent (two Haar handles of sizes m and n, the same
+ * storage type and stream) and S in R^{m x n} with diagonal s (min(m, n)
+ * entries) and zeros elsewhere: transpose = 0 answers y = Q x =
+ * U (S (V x)) (x: n entries, y: m), transpose = 1 answers y = Q' x =
+ * V' (S' (U' x)) (x: m entries, y: n); one query on each handle, the
+ * product with S formed in the first query's epilogue.  s, x, y: device
+ * vectors (storage type); x and y not aliased.  Errors: HD_ERR_INVALID
+ * (not two distinct Haar handles of equal storage and stream; null or
+ * aliased pointers), HD_ERR_CAPACITY, HD_ERR_NOMEM, HD_ERR_HIP. */
 int hd_usv_step(hd_handle U, hd_handle V, const void* s, int32_t transpose,
                 const void* x, void* y);
+
+/* Spectral method for generalized linear models (Sec. 2.2): on a Haar
+ * handle of size m (the m x m Q), with A = [I_n 0] Q (eq. (A_ortho)) for a
+ * signal dimension 1 <= n < m, measurements y_i = tanh|a_i' xi| and
+ * D = (1/m) A diag(y) A' (eq. (D_mtx)), runs K steps of the power iteration
+ * x_{k+1} = scale * m * D x_k from x_1.  The measurements take one query
+ * (A' xi = Q' [xi; 0]) and every step two (Q' [x_k; 0], then Q of y times
+ * that), 1 + 2K queries in all, the element-wise maps fused into the
+ * queries' epilogues.  scale keeps the iterates in range (the eigenvalues
+ * of m D lie in [0, 1)); the iterates are not normalised.
+ * xi, x1: device vectors of n entries.  z: NULL or device m entries
+ * receiving A' xi.  X: NULL or device (K+1) x n row-major receiving
+ * x_1 .. x_{K+1}.  Stream-ordered; uses six work vectors of the handle
+ * (allocated on first use).  Errors: HD_ERR_INVALID (not a Haar handle,
+ * n >= m, K < 0, non-finite scale, null or aliased pointers),
+ * HD_ERR_CAPACITY (1 + 2K more queries than t_max allows; checked before
+ * any work), HD_ERR_NOMEM, HD_ERR_HIP. */
+int hd_spectral_power(hd_handle h, int64_t n, const void* xi, const void* x1,
+                      int32_t K, double scale, void* z, void* X);
 
 /* ------------------------------------------------------------------------
  * Checkpoint and resume.  The state of a handle after its last query is

@@ -227,13 +227,48 @@ def goe_query(orc, x):
 
 
 def usv_query(orc_u, orc_v, s, x, transpose=False):
-    """Q = U diag(s) V with U, V independent lazy Haar matrices (section
-    "Other Random Matrix Ensembles", square case): Q x = U (s * (V x)),
-    Q' x = V' (s * (U' x))."""
+    """Q = U S V with U ~ Haar(m), V ~ Haar(n) independent lazy matrices and
+    S the m x n matrix with diagonal s (min(m, n) entries) and zeros
+    elsewhere (section "Other Random Matrix Ensembles"):
+    Q x = U (S (V x)) and Q' x = V' (S' (U' x))."""
     x = np.asarray(x, np.float64)
+    s = np.asarray(s, np.float64)
+    m, n = orc_u.n, orc_v.n
+    p = min(m, n)
     if transpose:
-        return orc_v.query(s * orc_u.query(x, True), True)
-    return orc_u.query(s * orc_v.query(x, False), False)
+        u = orc_u.query(x, True)
+        w = np.zeros(n)
+        w[:p] = s[:p] * u[:p]
+        return orc_v.query(w, True)
+    v = orc_v.query(x, False)
+    w = np.zeros(m)
+    w[:p] = s[:p] * v[:p]
+    return orc_u.query(w, False)
+
+
+def spectral_power(orc, xi, x1, K, scale=1.0):
+    """Spectral method of Sec. 2.2 on a lazy Haar Q of size m (the oracle
+    `orc`), with A = [I_n 0] Q (eq. (A_ortho)), measurements
+    y_i = tanh|a_i' xi| and D = (1/m) A diag(y) A' (eq. (D_mtx)).
+
+    The measurements take one query: A' xi = Q' [xi; 0].  Each power step
+    x_{k+1} = scale * m * D x_k takes two: u = Q' [x_k; 0], then
+    v = Q (y * u), of which x_{k+1} keeps the first n entries (times scale).
+    Returns (A' xi, X) with X = [x_1, ..., x_{K+1}]."""
+    xi = np.asarray(xi, np.float64)
+    n = xi.size
+    m = orc.n
+    pad = np.zeros(m - n)
+    z = orc.query(np.concatenate([xi, pad]), True)
+    y = np.tanh(np.abs(z))
+    x = np.asarray(x1, np.float64)
+    X = [x]
+    for _ in range(K):
+        u = orc.query(np.concatenate([x, pad]), True)
+        v = orc.query(y * u, False)
+        x = scale * v[:n]
+        X.append(x)
+    return z, np.array(X)
 
 
 def replay(orc, xs, transposes):

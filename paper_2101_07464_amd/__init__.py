@@ -67,8 +67,9 @@ class LazyMatrix:
         self._h = h
 
     def goe_mv(self, x):
-        """y = Q x + Q' x (``hd_goe_step``): G x for G = (Q + Q') of a square
-        Gaussian handle, two queries.  See ``LazyGOE``."""
+        """y = (Q x + Q' x)/sqrt(2) (``hd_goe_step``): G x for the GOE matrix
+        G = (Q + Q')/sqrt(2) of a square Gaussian handle, two queries.  See
+        ``LazyGOE``."""
         torch = _torch()
         x = self._vec(x, self.n)
         y = torch.empty(self.n, dtype=self.dtype, device=self.device)
@@ -168,6 +169,26 @@ class LazyMatrix:
                       vp(xo.data_ptr()), None, None)
         _lib.check(rc, "hd_run")
         return xo, None
+
+    def spectral_power(self, xi, x1, K, scale=1.0):
+        """Spectral method of Sec. 2.2 on this Haar handle of size m
+        (``hd_spectral_power``): A = [I_n 0] Q with n = len(xi) < m,
+        measurements y = tanh|A' xi|, and K power steps
+        x_{k+1} = scale * A diag(y) A' x_k.  Returns (A' xi, X) with
+        X[k] = x_{k+1}, (K+1) x n."""
+        torch = _torch()
+        n = int(xi.numel())
+        xi = self._vec(xi, n)
+        x1 = self._vec(x1, n)
+        z = torch.empty(self.m, dtype=self.dtype, device=self.device)
+        X = torch.empty((K + 1, n), dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_spectral_power(
+            self._h, n, ctypes.c_void_p(xi.data_ptr()),
+            ctypes.c_void_p(x1.data_ptr()), int(K), float(scale),
+            ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(X.data_ptr())),
+            "hd_spectral_power")
+        return z, X
 
     def lista_forward(self, a, theta, x1, y):
         """Unrolled ISTA layers (see ``hd_lista_forward``): returns
@@ -425,16 +446,15 @@ def autotune_clear():
 
 class LazyGOE(LazyMatrix):
     """Lazy n x n matrix G ~ scale * GOE(n) (symmetric; diagonal entries
-    N(0, 2 scale^2), off-diagonal N(0, scale^2)), built from a lazy Gaussian
-    Q with N(0, scale^2 / 2) entries as G = Q + Q'.  ``mv`` answers G x with
-    two queries of Q, so t_max counts queries of Q (two per call)."""
+    N(0, 2 scale^2), off-diagonal N(0, scale^2)), G = (Q + Q')/sqrt(2) for a
+    lazy Gaussian Q with N(0, scale^2) entries.  ``mv`` answers G x with two
+    queries of Q (``hd_goe_step``), so t_max counts queries of Q (two per
+    call)."""
 
     def __init__(self, n, t_max=None, seed=0, trial=0, scale=1.0, dtype=None,
                  device="cuda:0"):
-        import math
         super().__init__(GINIBRE, n, t_max=t_max, seed=seed, trial=trial,
-                         sigma=scale / math.sqrt(2.0), dtype=dtype,
-                         device=device)
+                         sigma=scale, dtype=dtype, device=device)
         self.scale = scale
 
     def mv(self, x):
@@ -449,14 +469,16 @@ class LazyGOE(LazyMatrix):
 
 
 def usv_mv(U, V, s, x, transpose=False):
-    """y = Q x (or Q' x) for Q = U diag(s) V with U, V two Haar LazyMatrix
-    handles of the same n, dtype and device (``hd_usv_step``)."""
+    """y = Q x (or Q' x) for Q = U S V with U, V two Haar LazyMatrix handles
+    of sizes m and n (same dtype and device) and S = diag(s) in R^{m x n}
+    (s: min(m, n) entries) (``hd_usv_step``)."""
     torch = _torch()
-    if U.device != V.device or U.dtype != V.dtype or U.n != V.n:
-        raise ValueError("U and V must match in n, dtype and device")
-    x = U._vec(x, U.n)
-    s = U._vec(s, U.n)
-    y = torch.empty(U.n, dtype=U.dtype, device=U.device)
+    if U.device != V.device or U.dtype != V.dtype:
+        raise ValueError("U and V must match in dtype and device")
+    m, n = U.n, V.n
+    x = U._vec(x, m if transpose else n)
+    s = U._vec(s, min(m, n))
+    y = torch.empty(n if transpose else m, dtype=U.dtype, device=U.device)
     U._sync_stream()
     V._sync_stream()
     _lib.check(_lib.load().hd_usv_step(

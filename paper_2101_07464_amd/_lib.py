@@ -39,7 +39,7 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
            "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
-           "hd_noalloc_scratch_bytes"]
+           "hd_noalloc_scratch_bytes", "hd_spectral_power"]
 
 
 class HDConfig(ctypes.Structure):
@@ -121,6 +121,7 @@ def load():
                                  vp, vp, vp]),
         "hd_noalloc_scratch_bytes": (i32, [P(HDConfig),
                                            P(ctypes.c_size_t)]),
+        "hd_spectral_power": (i32, [vp, i64, vp, vp, i32, dbl, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -1162,17 +1162,11 @@ int hd_pivots(hd_handle h, int32_t side, int32_t count, double* nu,
   return HD_OK;
 }
 
-int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
-           const void* x0, void* x_out, void* traj_x, void* traj_y) {
-  if (!h || !dyn || !x1 || T < 0) return HD_ERR_INVALID;
-  if (h->cfg.m != h->cfg.n) return HD_ERR_INVALID;
-  if (dyn->kind < HD_DYN_TANH || dyn->kind > HD_DYN_NORMALIZE)
-    return HD_ERR_INVALID;
-  // The normalising map is switched off: its one run on the GPU ended in a
-  // memory-aperture fault whose cause has not been shown (host emulation of
-  // the same launches under AddressSanitizer is clean).  It stays off until
-  // that cause is found.
-  if (dyn->kind == HD_DYN_NORMALIZE) return HD_ERR_UNSUPPORTED;
+// hd_run after its argument checks: T steps of a built-in map (every map,
+// including the normalising one that hd_run refuses).
+static int run_dynamics(hd_handle h, const hd_dynamics* dyn, int32_t T,
+                        const void* x1, const void* x0, void* x_out,
+                        void* traj_x, void* traj_y) {
   if (dyn->pattern != HD_PATTERN_Q && dyn->pattern != HD_PATTERN_ALT)
     return HD_ERR_INVALID;
   if ((int64_t)h->t + T > h->cfg.t_max) return HD_ERR_CAPACITY;
@@ -1246,6 +1240,20 @@ int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
   return HD_OK;
 }
 
+int hd_run(hd_handle h, const hd_dynamics* dyn, int32_t T, const void* x1,
+           const void* x0, void* x_out, void* traj_x, void* traj_y) {
+  if (!h || !dyn || !x1 || T < 0) return HD_ERR_INVALID;
+  if (h->cfg.m != h->cfg.n) return HD_ERR_INVALID;
+  if (dyn->kind < HD_DYN_TANH || dyn->kind > HD_DYN_NORMALIZE)
+    return HD_ERR_INVALID;
+  // The normalising map is switched off: its one run on the GPU ended in a
+  // memory-aperture fault whose cause has not been shown (the CPU emulation
+  // of exactly this path in tests/emu is clean and matches the oracle).  It
+  // stays off until a cause is found.
+  if (dyn->kind == HD_DYN_NORMALIZE) return HD_ERR_UNSUPPORTED;
+  return run_dynamics(h, dyn, T, x1, x0, x_out, traj_x, traj_y);
+}
+
 // Work buffers of the unrolled-ISTA entry points, allocated on first use.
 static int ista_buffers(hd_ctx* h) {
   if (h->ista[0]) return HD_OK;
@@ -1274,10 +1282,11 @@ int hd_goe_step(hd_handle h, const void* x, void* y) {
   rc = query(h, 0, x, qx, 0, no_dyn());
   h->hint = -1;
   if (rc) return rc;
-  // y = Q x + Q' x, formed in the second query's epilogue
+  // y = (Q x + Q' x) / sqrt(2), formed in the second query's epilogue
   DynFuse f = no_dyn();
   f.kind = kDynAxpy;
-  f.a = -1.0;
+  f.a = -M_SQRT1_2;
+  f.b = M_SQRT1_2;
   f.x = qx;
   f.xnext = y;
   return query(h, 1, x, qtx, 0, f);
@@ -1288,24 +1297,99 @@ int hd_usv_step(hd_handle U, hd_handle V, const void* s, int32_t transpose,
   if (!U || !V || U == V || !s || !x || !y || x == y) return HD_ERR_INVALID;
   if (transpose != 0 && transpose != 1) return HD_ERR_INVALID;
   if (U->cfg.ensemble != HD_HAAR || V->cfg.ensemble != HD_HAAR ||
-      U->cfg.n != V->cfg.n || U->cfg.storage != V->cfg.storage ||
-      U->stream != V->stream)
+      U->cfg.storage != V->cfg.storage || U->stream != V->stream)
     return HD_ERR_INVALID;
-  // y = U (s .* (V x)), or y = V' (s .* (U' x)): the first handle's query
-  // forms s .* (its answer) in its epilogue, the second answers that
+  // y = U (S (V x)), or y = V' (S' (U' x)) with S = diag(s) in R^{m x n}:
+  // the first handle's query forms the first min(m, n) entries of S times
+  // its answer in its epilogue (into the second handle's work vector, whose
+  // other entries are zero), the second answers that
   hd_ctx* first = transpose ? U : V;
   hd_ctx* second = transpose ? V : U;
   if (first->t >= first->cfg.t_max || second->t >= second->cfg.t_max)
     return HD_ERR_CAPACITY;
   int rc = ista_buffers(first);
+  if (!rc) rc = ista_buffers(second);
   if (rc) return rc;
+  const int64_t d1 = first->cfg.n, d2 = second->cfg.n;
+  const int64_t p = d1 < d2 ? d1 : d2;
+  void* mid = second->ista[1];
+  if (d2 > d1)
+    LCHK(launch_zero((char*)mid + (size_t)first->es * (size_t)d1,
+                     (size_t)first->es * (size_t)(d2 - d1), first->stream));
   DynFuse f = no_dyn();
   f.kind = kDynScale;
   f.x = s;
-  f.xnext = first->ista[1];
+  f.len = p;
+  f.xnext = mid;
   rc = query(first, transpose, x, first->ista[0], 0, f);
   if (rc) return rc;
-  return query(second, transpose, first->ista[1], y, 0, no_dyn());
+  return query(second, transpose, mid, y, 0, no_dyn());
+}
+
+int hd_spectral_power(hd_handle h, int64_t n, const void* xi, const void* x1,
+                      int32_t K, double scale, void* z, void* X) {
+  if (!h || !xi || !x1 || K < 0 || n < 1) return HD_ERR_INVALID;
+  if (h->cfg.ensemble != HD_HAAR || n >= h->cfg.n || !std::isfinite(scale))
+    return HD_ERR_INVALID;
+  if (z == xi || X == xi || (X && X == z)) return HD_ERR_INVALID;
+  if ((int64_t)h->t + 1 + 2 * (int64_t)K > h->cfg.t_max)
+    return HD_ERR_CAPACITY;
+  int rc = ista_buffers(h);  // six work vectors of m entries
+  if (rc) return rc;
+  const int64_t m = h->cfg.n;
+  const size_t es = (size_t)h->es;
+  void* pad[2] = {h->ista[0], h->ista[5]};  // query inputs [x; 0]
+  void* wts = h->ista[1];                     // y = tanh|A' xi|
+  void* u = h->ista[2];
+  void* w = h->ista[3];
+  void* v = h->ista[4];
+  // [xi; 0]; the tail stays zero in both input buffers (the head-keeping
+  // map writes zeros there)
+  LCHK(launch_zero((char*)pad[0] + es * (size_t)n, es * (size_t)(m - n),
+                   h->stream));
+  HIPC(hipMemcpyAsync(pad[0], xi, es * (size_t)n, hipMemcpyDeviceToDevice,
+                      h->stream));
+  // the measurements: A' xi = Q' [xi; 0], and y = tanh|A' xi| in the
+  // epilogue
+  DynFuse f0 = no_dyn();
+  f0.kind = kDynTanhAbs;
+  f0.a = 1.0;
+  f0.xnext = wts;
+  h->hint = K > 0 ? 1 : kHintNone;
+  rc = query(h, 1, pad[0], z ? z : u, 0, f0);
+  if (rc == HD_OK && K > 0) {
+    rc = hipMemcpyAsync(pad[0], x1, es * (size_t)n, hipMemcpyDeviceToDevice,
+                        h->stream) == hipSuccess ? HD_OK
+                                                 : hip_fail(hipGetLastError());
+    if (rc == HD_OK && X &&
+        hipMemcpyAsync(X, x1, es * (size_t)n, hipMemcpyDeviceToDevice,
+                       h->stream) != hipSuccess)
+      rc = hip_fail(hipGetLastError());
+  }
+  for (int k = 0; k < K && rc == HD_OK; ++k) {
+    // u = Q' [x_k; 0], then w = y .* u (epilogue)
+    DynFuse fa = no_dyn();
+    fa.kind = kDynScale;
+    fa.x = wts;
+    fa.xnext = w;
+    fa.next_input = 1;
+    h->hint = 0;
+    rc = query(h, 1, pad[k & 1], u, 0, fa);
+    if (rc) break;
+    // v = Q w; x_{k+1} = scale * v[:n] (epilogue: the next input [x; 0]
+    // and the row of X)
+    DynFuse fb = no_dyn();
+    fb.kind = kDynHead;
+    fb.a = scale;
+    fb.len = n;
+    fb.xnext = pad[(k + 1) & 1];
+    fb.aux = X ? (void*)((char*)X + es * (size_t)n * (size_t)(k + 1)) : v;
+    fb.next_input = k + 1 < K;
+    h->hint = k + 1 < K ? 1 : kHintNone;
+    rc = query(h, 0, w, v, 0, fb);
+  }
+  h->hint = -1;
+  return rc;
 }
 
 static int ista_room(const hd_ctx* h, int nq, int pq) {
@@ -1393,6 +1477,7 @@ int hd_lista_backward(hd_handle h, int32_t L, const float* a,
     DynFuse f = no_dyn();
     f.kind = kDynAxpy;
     f.a = a[t];
+    f.b = 1.0;
     f.x = gbar;
     f.xnext = t == 0 ? g_x1 : gnext;
     h->hint = t > 0 && (t > 1 || g_x1) ? 0 : -1;

@@ -102,8 +102,12 @@ enum DynKind {
   kDynNormalize = 3, // (unfused; see k_dyn)
   kDynResidual = 4,  // xnext = x - y                (x: the observation)
   kDynLista = 5,     // aux = v = x + a y; xnext = soft(v, b)
-  kDynAxpy = 6,      // xnext = x - a y
-  kDynScale = 7      // xnext = x y (x: a diagonal, entrywise)
+  kDynAxpy = 6,      // xnext = b x - a y
+  kDynScale = 7,     // xnext = x y (x: a diagonal, entrywise); with
+                     // len > 0 only rows < len (x and xnext of len rows)
+  kDynTanhAbs = 8,   // xnext = a tanh(|y|)
+  kDynHead = 9       // xnext = a y on rows < len, 0 below; aux = a y on
+                     // rows < len (a vector of len entries)
 };
 
 struct DynFuse {
@@ -112,7 +116,8 @@ struct DynFuse {
   const void* x;      // x_t
   const void* xprev;  // x_{t-1}
   void* xnext;        // x_{t+1}
-  void* aux;          // second output (kDynLista)
+  void* aux;          // second output (kDynLista, kDynHead)
+  int64_t len;        // kDynHead: rows kept; kDynScale: rows written
   int next_input;     // host only: xnext is the next query's input
 };
 
@@ -298,7 +303,7 @@ int launch_trial_small(int f64, int op, int ntrials, const TrialDev* d,
 int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
                            BatchMap m, hipStream_t s);
 
-// Device-to-device copies of 4-byte words, one workgroup per job.
+// Device-to-device copies of 4-byte words, one workgroup per job.// Device-to-device copies of 4-byte words, one workgroup per job.
 struct CopyJob {
   const void* src;
   void* dst;

@@ -14,7 +14,8 @@
 // per FP32 column, two per FP64 column), a chunk is the 256 rows of one
 // wave's 64 lanes, and a workgroup covers CPT chunks; its four waves split
 // the columns (wave w takes columns w, w + 4, w + 8, ...), so every wave has
-// a full chunk of rows in flight per column even when the panel is short.
+// a full chunk of rows in flight per column even when the panel is short
+// (the TDOT of four-chunk workgroups splits the rows instead; see rs_sweep).
 //   tdot     : w = V' b (column dots), optionally a second right-hand side
 //   pass     : out = Delta a - V z (GEMV-N), the new panel column, the dots of
 //              every column with the next query's Philox draw (prefetch) and,
@@ -174,6 +175,88 @@ __device__ __forceinline__ void sweep(
           if (owner) out1[wave + kWaves * q] = s1;
         }
       }
+    }
+  }
+}
+
+// ------------------------------------------ row-split four-chunk sweeps --
+//
+// The TDOT of a four-chunk workgroup splits the rows over the waves instead
+// of the columns: wave w owns chunk w (rows blk0 + 256 w + 4 lane + e) and
+// sweeps every column of the panel over it.  The right-hand sides and draws
+// of a lane are its own four rows (registers, no LDS copy: 104 VGPRs and four
+// waves per SIMD for two right-hand sides, against 146 and three in the
+// column split), and the column dots are added over the four waves through
+// LDS, a block of kRsBlk columns at a time (fixed order).  The GEMV-N passes
+// keep the column split: the row-split form of them (no LDS row sums, 124
+// VGPRs) measured no faster at n = 1e7.
+
+constexpr int kRsCG = 8;     // columns per group of a wave's sweep
+constexpr int kRsBlk = 256;  // columns per block of the cross-wave dot sums
+
+// Sweep of columns [0, nc) over the lane's four rows starting at row0 (ND
+// dot streams with r0 / r1 into out0 / out1, GEMV-N acc -= V z when NZ).
+// Every thread of the workgroup calls it with the same nc (it contains
+// barriers when ND > 0).  dl holds ND * kWaves * kRsBlk doubles.
+template <typename T, int ND, int NZ, bool NT>
+__device__ __forceinline__ void rs_sweep(
+    const T* __restrict__ V, int64_t ld, int nc, int64_t row0,
+    const double (&r0)[4], const double (&r1)[4],
+    const double* __restrict__ z, double (&acc)[4], double* dl,
+    double* out0, double* out1) {
+  constexpr int kGroup = 64 / kRsCG;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const T* __restrict__ Vl = V + row0;
+#pragma unroll 1
+  for (int jb = 0; jb < nc; jb += kRsBlk) {
+    const int je = min(nc, jb + kRsBlk);
+#pragma unroll 1
+    for (int g0 = jb; g0 < je; g0 += kRsCG) {
+      double p0[kRsCG], p1[ND == 2 ? kRsCG : 1], q[NZ ? kRsCG : 1];
+      double v[kRsCG][4];
+#pragma unroll
+      for (int jj = 0; jj < kRsCG; ++jj) {
+        const int j = min(g0 + jj, je - 1);
+        load4<NT>(Vl + (int64_t)j * ld, v[jj]);
+        if constexpr (NZ) q[jj] = g0 + jj < je ? z[g0 + jj] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < kRsCG; ++jj) {
+        p0[jj] = 0.0;
+        if constexpr (ND == 2) p1[jj] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (NZ) acc[e] -= v[jj][e] * q[jj];
+          if constexpr (ND >= 1) p0[jj] += v[jj][e] * r0[e];
+          if constexpr (ND == 2) p1[jj] += v[jj][e] * r1[e];
+        }
+      }
+      if constexpr (ND >= 1) {
+        const int jl = g0 - jb + lane / kGroup;
+        const bool owner = (lane % kGroup) == 0 && g0 + lane / kGroup < je;
+        const double s0 = wave_reduce_scatter<kRsCG>(p0);
+        if (owner) dl[wave * kRsBlk + jl] = s0;
+        if constexpr (ND == 2) {
+          const double s1 = wave_reduce_scatter<kRsCG>(p1);
+          if (owner) dl[(kWaves + wave) * kRsBlk + jl] = s1;
+        }
+      }
+    }
+    if constexpr (ND >= 1) {
+      __syncthreads();
+      const int t = threadIdx.x;
+      if (t < je - jb) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          s0 += dl[w * kRsBlk + t];
+          if constexpr (ND == 2) s1 += dl[(kWaves + w) * kRsBlk + t];
+        }
+        out0[jb + t] = s0;
+        if constexpr (ND == 2) out1[jb + t] = s1;
+      }
+      __syncthreads();
     }
   }
 }
@@ -458,8 +541,21 @@ __device__ __forceinline__ double soft(double v, double th) {
 template <typename T>
 __device__ __forceinline__ double dyn_store(const DynFuse& d, int64_t i,
                                             double y) {
-  const double x = (double)((const T*)d.x)[i];
   double out;
+  if (d.kind == kDynTanhAbs || d.kind == kDynHead) {
+    // maps of y alone (d.x is not read)
+    if (d.kind == kDynTanhAbs) {
+      out = d.a * tanh(fabs(y));
+    } else {
+      out = i < d.len ? d.a * y : 0.0;
+      if (i < d.len) ((T*)d.aux)[i] = (T)out;
+    }
+    const T st = (T)out;
+    ((T*)d.xnext)[i] = st;
+    return (double)st;
+  }
+  if (d.kind == kDynScale && d.len > 0 && i >= d.len) return 0.0;
+  const double x = (double)((const T*)d.x)[i];
   if (d.kind == kDynTanh) {
     out = tanh(d.a * y) + d.b * x;
   } else if (d.kind == kDynSoftHist) {
@@ -473,7 +569,7 @@ __device__ __forceinline__ double dyn_store(const DynFuse& d, int64_t i,
   } else if (d.kind == kDynScale) {
     out = x * y;  // a diagonal matrix times y
   } else {  // kDynAxpy
-    out = x - d.a * y;
+    out = d.b * x - d.a * y;
   }
   const T stored = (T)out;
   ((T*)d.xnext)[i] = stored;
@@ -482,8 +578,46 @@ __device__ __forceinline__ double dyn_store(const DynFuse& d, int64_t i,
 
 // ------------------------------------------------------------------ TDOT --
 
+// TDOT of a four-chunk workgroup in the row-split layout.
+template <typename T, bool GEN, bool TWO>
+__device__ __forceinline__ void tdot_rs(const TdotArgs& a, int blk) {
+  __shared__ double dl[(TWO ? 2 : 1) * kWaves * kRsBlk];
+  __shared__ double scr[kWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 =
+      (int64_t)blk * (kChunkRows * 4) + wave * kChunkRows + 4 * lane;
+  const PhiloxKey key{a.key.k0, a.key.k1};
+  double r0[4], r1[4];
+  if (GEN) draw_rows<T>(key, a.gen_step, row0, a.lo, a.n, true, r0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = row0 + e;
+    if (!GEN) r0[e] = (i < a.n && i > a.lo) ? (double)((const T*)a.b)[i] : 0.0;
+    r1[e] = (TWO && i < a.n) ? (double)((const T*)a.b2)[i] : 0.0;
+  }
+  double* out = a.partials + (int64_t)blk * a.pstride;
+  double acc[4];
+  rs_sweep<T, TWO ? 2 : 1, 0, true>((const T*)a.V, a.ld, a.ncols, row0, r0,
+                                    r1, nullptr, acc, dl, out,
+                                    out + a.slot2);
+  if (a.ncols2 > 0)
+    rs_sweep<T, 1, 0, true>((const T*)a.V2, a.ld, a.ncols2, row0, r0, r1,
+                            nullptr, acc, dl, out + a.ncols, nullptr);
+  if (a.want_ss) {
+    double ss = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ss += r0[e] * r0[e];
+    const double s = block_sum(ss, scr);
+    if (tid == 0) out[a.extra + kSlotPFSS] = s;
+  }
+}
+
 template <typename T, int CPT, bool GEN, bool TWO>
 __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
+  if constexpr (CPT == 4) {
+    tdot_rs<T, GEN, TWO>(a, blk);
+    return;
+  }
   __shared__ double g[GEN ? CPT * kChunkRows : 1];
   __shared__ double scr[kWaves];
   const int tid = threadIdx.x, lane = tid & 63;

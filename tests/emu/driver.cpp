@@ -1,0 +1,83 @@
+// CPU emulation driver: runs the library's own trajectory code (the real
+// runtime and kernel sources, emulated on the host by emu.cpp) for one
+// configuration and writes the recorded x_t and y_t.
+//
+// usage: driver ENS N T KIND A B PATTERN SEED TRIAL F64 CPT X1_FILE OUT_PREFIX
+//   ENS 0 Gaussian (sigma = 1/sqrt(N)) / 1 Haar; KIND as HD_DYN_*; PATTERN
+//   0 = Q only, 1 = alternating; CPT 0 = the built-in shape, else forced;
+//   X1_FILE holds N values of the storage type.  Writes OUT_PREFIX.X
+//   ((T+1) x N) and OUT_PREFIX.Y (T x N) and prints "rc <code> status <code>".
+#include "hd_api.hip"
+
+#include <cstdio>
+#include <cstdlib>
+
+static void* read_file(const char* path, size_t bytes) {
+  void* p = std::malloc(bytes);
+  FILE* f = std::fopen(path, "rb");
+  if (!f || std::fread(p, 1, bytes, f) != bytes) {
+    std::fprintf(stderr, "cannot read %s\n", path);
+    std::exit(2);
+  }
+  std::fclose(f);
+  return p;
+}
+
+static void write_file(const char* path, const void* p, size_t bytes) {
+  FILE* f = std::fopen(path, "wb");
+  if (!f || std::fwrite(p, 1, bytes, f) != bytes) {
+    std::fprintf(stderr, "cannot write %s\n", path);
+    std::exit(2);
+  }
+  std::fclose(f);
+}
+
+int main(int argc, char** argv) {
+  if (argc != 14) {
+    std::fprintf(stderr, "usage: see the header of driver.cpp\n");
+    return 2;
+  }
+  const int ens = std::atoi(argv[1]);
+  const int64_t n = std::atoll(argv[2]);
+  const int T = std::atoi(argv[3]);
+  hd_dynamics dyn;
+  dyn.kind = std::atoi(argv[4]);
+  dyn.a = std::atof(argv[5]);
+  dyn.b = std::atof(argv[6]);
+  dyn.pattern = std::atoi(argv[7]);
+  const uint32_t seed = (uint32_t)std::atol(argv[8]);
+  const uint32_t trial = (uint32_t)std::atol(argv[9]);
+  const int f64 = std::atoi(argv[10]);
+  const int cpt = std::atoi(argv[11]);
+  if (cpt) setenv("HD_CPT", argv[11], 1);
+  hd_config cfg;
+  std::memset(&cfg, 0, sizeof(cfg));
+  cfg.ensemble = ens;
+  cfg.storage = f64 ? HD_F64 : HD_F32;
+  cfg.m = cfg.n = n;
+  cfg.t_max = T;
+  cfg.seed = seed;
+  cfg.trial = trial;
+  cfg.sigma = 1.0 / std::sqrt((double)n);
+  hd_handle h = nullptr;
+  int rc = hd_init(&cfg, &h);
+  if (rc) {
+    std::printf("rc %d status 0\n", rc);
+    return 1;
+  }
+  const size_t es = f64 ? 8 : 4;
+  void* x1 = read_file(argv[12], es * (size_t)n);
+  void* X = std::malloc(es * (size_t)n * (size_t)(T + 1));
+  void* Y = std::malloc(es * (size_t)n * (size_t)T);
+  rc = run_dynamics(h, &dyn, T, x1, nullptr, nullptr, X, Y);
+  const int st = hd_status(h);
+  std::string pre = argv[13];
+  write_file((pre + ".X").c_str(), X, es * (size_t)n * (size_t)(T + 1));
+  write_file((pre + ".Y").c_str(), Y, es * (size_t)n * (size_t)T);
+  std::printf("rc %d status %d\n", rc, st);
+  hd_free(h);
+  std::free(x1);
+  std::free(X);
+  std::free(Y);
+  return rc ? 1 : 0;
+}

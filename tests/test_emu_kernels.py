@@ -1,0 +1,101 @@
+"""The library's runtime and kernel sources, emulated on the host under
+AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+
+tests/emu holds a host emulation of the HIP features the sources use: every
+workgroup runs as cooperative fibers, barriers and wave-wide exchanges
+(shuffles, DPP moves, permlane swaps) synchronise the fibers involved, and a
+barrier some participant cannot reach aborts.  Device buffers are exact-size
+host allocations, so any access beyond a buffer the runtime allocated, or
+beyond a caller's vector, is reported by AddressSanitizer.
+
+The normalising map x_{t+1} = y/||y|| + 0.1 x (the large single trial's
+dynamics, switched off on the GPU after a fault whose cause was never shown)
+runs here through exactly the launches hd_run would issue for it (Haar,
+n = 4099, T = 30, FP32, the case of that fault): it must be clean under both
+sanitizers and agree with the FP64 oracle.  A Gaussian trajectory with Q and
+Q' alternating in the four-chunk launch shape covers the other ensemble and
+the row-split column dots.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_07464_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CLANG = "/opt/rocm/llvm/bin/clang++"
+EMU = os.path.join(ROOT, "tests", "emu")
+CSRC = os.path.join(ROOT, "paper_2101_07464_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if not os.path.exists(CLANG):
+        pytest.skip("clang++ of the ROCm toolchain not found")
+    out = str(tmp_path_factory.mktemp("emu") / "emu_driver")
+    cmd = [CLANG, "-std=c++17", "-O2", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           "-Wno-unused-command-line-argument",
+           "-I", os.path.join(EMU, "shim"), "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, "-x", "c++", os.path.join(EMU, "driver.cpp"),
+           "-x", "c++", os.path.join(CSRC, "hd_kernels.hip"),
+           "-x", "c++", os.path.join(EMU, "emu.cpp"), "-o", out]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _run(driver, tmp_path, ens, n, T, kind, a, b, pattern, seed, cpt, x1):
+    xf = str(tmp_path / "x1.bin")
+    x1.astype(np.float32).tofile(xf)
+    pre = str(tmp_path / "out")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([driver, str(ens), str(n), str(T), str(kind), str(a),
+                        str(b), str(pattern), str(seed), "0", "0", str(cpt),
+                        xf, pre], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
+    X = np.fromfile(pre + ".X", dtype=np.float32).reshape(T + 1, n)
+    Y = np.fromfile(pre + ".Y", dtype=np.float32).reshape(T, n)
+    return X.astype(np.float64), Y.astype(np.float64)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_normalising_map_emulated(driver, tmp_path):
+    n, T, seed = 4099, 30, 2
+    x1 = inputs.x1_normal(n, seed=seed).astype(np.float32)
+    X, Y = _run(driver, tmp_path, 1, n, T, 3, 0.0, 0.1, 0, seed, 0, x1)
+    # mode B: the oracle answers the emulated run's own query vectors
+    orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=seed)
+    Yb = oracle.replay(orc, X[:-1], [False] * T)
+    eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
+    # mode A: the oracle's own FP64 trajectory of the same map
+    orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=seed)
+    Xo, _ = oracle.run_trajectory(orc, X[0], T, "normalize", 0.0, 0.1)
+    ea = max(relerr(x, xo) for x, xo in zip(X, Xo))
+    print("emulated normalising map: mode B %.2e  mode A %.2e" % (eb, ea))
+    assert eb < 1e-4 and ea < 1e-4
+    # the map's own invariant: x_{t+1} - 0.1 x_t has unit norm
+    d = np.linalg.norm(X[1:] - 0.1 * X[:-1], axis=1)
+    assert np.allclose(d, 1.0, atol=1e-5)
+
+
+def test_gaussian_alternating_four_chunks_emulated(driver, tmp_path):
+    n, T, seed = 2000, 8, 7
+    x1 = inputs.x1_normal(n, seed=seed, scale=1.0).astype(np.float32)
+    X, Y = _run(driver, tmp_path, 0, n, T, 2, 0.1, 0.3, 1, seed, 4, x1)
+    orc = oracle.HDOracle(oracle.GINIBRE, n, tmax=T, seed=seed,
+                          sigma=1.0 / np.sqrt(n))
+    Yb = oracle.replay(orc, X[:-1], [t % 2 == 1 for t in range(T)])
+    eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
+    print("emulated Gaussian, four chunks: mode B %.2e" % eb)
+    assert eb < 1e-4

@@ -301,26 +301,30 @@ def test_goe_entry_variances():
     assert abs(cols.mean(axis=0)).max() < 5 * sig * np.sqrt(2.0 / trials)
 
 
-def test_usv_exact_reconstruction_and_singular_values():
-    """Section "Other Random Matrix Ensembles", Q = U diag(s) V: every
-    answer (Q and Q' queries, mixed) equals that of U_rec diag(s) V_rec for
-    any completions of the two lazy Haar matrices, whose singular values
-    are |s|."""
-    n, K = 12, 6
-    rng = np.random.default_rng(8)
-    s = rng.standard_normal(n) * 2.0
-    ou = HDOracle(HAAR, n, seed=3, trial=1)
+@pytest.mark.parametrize("m,n", [(12, 12), (15, 9), (8, 13)])
+def test_usv_exact_reconstruction_and_singular_values(m, n):
+    """Section "Other Random Matrix Ensembles", Q = U S V with U ~ Haar(m),
+    V ~ Haar(n) and S = diag(s) in R^{m x n}: every answer (Q and Q'
+    queries, mixed) equals that of U_rec S V_rec for any completions of the
+    two lazy Haar matrices, whose singular values are |s|."""
+    K = 6
+    p = min(m, n)
+    rng = np.random.default_rng(8 + m + n)
+    s = rng.standard_normal(p) * 2.0
+    ou = HDOracle(HAAR, m, seed=3, trial=1)
     ov = HDOracle(HAAR, n, seed=3, trial=2)
     hist = []
     for k in range(K):
         tr = bool(rng.random() < 0.5)
-        x = rng.standard_normal(n)
+        x = rng.standard_normal(m if tr else n)
         hist.append((tr, x, oracle.usv_query(ou, ov, s, x, tr)))
     assert ou.counts()[0] == K and ov.counts()[0] == K
+    S = np.zeros((m, n))
+    S[np.arange(p), np.arange(p)] = s
     for _ in range(2):
-        Ur = _haar_rec(ou, n, K, haar_dense(n - K, rng))
+        Ur = _haar_rec(ou, m, K, haar_dense(m - K, rng))
         Vr = _haar_rec(ov, n, K, haar_dense(n - K, rng))
-        Qr = Ur @ np.diag(s) @ Vr
+        Qr = Ur @ S @ Vr
         for tr, x, y in hist:
             assert np.allclose((Qr.T if tr else Qr) @ x, y, atol=1e-12)
         sv = np.linalg.svd(Qr, compute_uv=False)
@@ -530,3 +534,52 @@ def test_normalising_trajectory_on_haar_keeps_unit_norm():
     assert np.allclose(np.linalg.norm(X[1:], axis=1), 1.0, atol=1e-13)
     assert np.allclose(np.linalg.norm(Y, axis=1),
                        np.linalg.norm(X[:-1], axis=1), rtol=1e-13)
+
+
+def _spectral_dense(orc, m, n, t, rng):
+    """A = [I_n 0] Q_rec (eq. (A_ortho)) for the oracle's lazy Haar Q after
+    t queries, completed with a random orthogonal W."""
+    Qr = _haar_rec(orc, m, t, haar_dense(m - t, rng))
+    return Qr[:n, :]
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.5])
+def test_spectral_power_matches_dense_matrix(scale):
+    """Sec. 2.2: the measurements are A' xi, and every power step of the
+    oracle's spectral method is x_{k+1} = scale * A diag(y) A' x_k with
+    y = tanh|A' xi| (m D of eq. (D_mtx)), for the dense A rebuilt from the
+    revealed reflectors (any completion)."""
+    m, n, K = 30, 12, 7
+    rng = np.random.default_rng(40)
+    orc = HDOracle(HAAR, m, seed=3, trial=1)
+    xi = rng.standard_normal(n)
+    x1 = rng.standard_normal(n)
+    z, X = oracle.spectral_power(orc, xi, x1, K, scale)
+    assert orc.counts()[0] == 1 + 2 * K
+    for _ in range(2):
+        A = _spectral_dense(orc, m, n, 1 + 2 * K, rng)
+        assert np.allclose(A @ A.T, np.eye(n), atol=1e-12)
+        assert np.allclose(z, A.T @ xi, atol=1e-12)
+        Dm = A @ np.diag(np.tanh(np.abs(A.T @ xi))) @ A.T
+        for k in range(K):
+            assert np.allclose(X[k + 1], scale * Dm @ X[k], atol=1e-12)
+
+
+def test_spectral_power_converges_to_top_eigenvector():
+    """Power iteration on D (eq. (D_mtx)) through the lazy matrix ends at
+    the leading eigenvector of the dense D built from the revealed
+    reflectors, and its Rayleigh quotients never decrease (D is symmetric
+    positive semidefinite)."""
+    m, n, K = 500, 100, 180
+    rng = np.random.default_rng(41)
+    orc = HDOracle(HAAR, m, seed=5)
+    xi = rng.standard_normal(n)
+    z, X = oracle.spectral_power(orc, xi, rng.standard_normal(n), K, 1.0)
+    A = _spectral_dense(orc, m, n, 1 + 2 * K, rng)
+    ev, U = np.linalg.eigh(A @ np.diag(np.tanh(np.abs(z))) @ A.T)
+    x = X[-1] / np.linalg.norm(X[-1])
+    assert ev[-1] - ev[-2] > 0.05 * ev[-1]
+    assert abs(x @ U[:, -1]) > 1 - 1e-9
+    rq = [X[k] @ X[k + 1] / (X[k] @ X[k]) for k in range(K)]
+    assert all(b >= a - 1e-12 for a, b in zip(rq, rq[1:]))
+    assert abs(rq[-1] - ev[-1]) < 1e-9 * ev[-1]
