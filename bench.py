@@ -555,6 +555,98 @@ def main_spectral(args):
     print(json.dumps(out), flush=True)
 
 
+LASSO = dict(name="lasso_ista_n1000_m500_T50_trials1e5_fp32", n=1000, m=500,
+             L=50, count=100_000, lam=2.0, tau=0.3, rho=0.2, sig_s=2.0,
+             sig_w=0.1, direct_trials=20_000)
+
+
+def main_lasso(args):
+    """The lasso experiment of Sec. 2.1 (the paper's first figure): 1e5
+    independent trials of ISTA (eq. (ista)) on Gaussian Q (m = n/2,
+    N(0, 1/m) entries), n = 1000, T = 50, lambda = 2, tau = 0.3,
+    rho = 0.2, sigma_s = 2, sigma_w = 0.1, all trials in one lockstep batch
+    (hd_ista_run).  A step runs every trial to the end.  Beside it, the
+    direct method (dense Q drawn first, dense products, on the same GPU) on
+    a sample of trials, with the mean squared error curves compared."""
+    import torch
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import inputs
+    dev = "cuda:0"
+    c = LASSO
+    n, m, L, C = c["n"], c["m"], c["L"], c["count"]
+    sig = 1.0 / np.sqrt(m)
+    xs_h, w_h = inputs.lasso_batch(C, n, m, 1 - c["rho"], c["sig_s"],
+                                   c["sig_w"], seed=0)
+    xs = torch.from_numpy(xs_h).to(dev, torch.float32)
+    w = torch.from_numpy(w_h).to(dev, torch.float32)
+    del xs_h, w_h
+    a = [c["tau"]] * L
+    th = [c["lam"] * c["tau"]] * L
+    B = hd.IstaBatch(m, n, L, C, seed=0, trial0=0, sigma=sig, device=dev)
+    for _ in range(args.warmup):
+        X = B.run(a, th, xs, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X = B.run(a, th, xs, w)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if B.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    e_hd = ((X - xs.unsqueeze(1)).double().pow(2).sum(2) / n).mean(0)
+    e_hd = e_hd.cpu().numpy()
+    del X, B
+    torch.cuda.empty_cache()
+    # the direct method on a sample of trials (independent inputs)
+    D = c["direct_trials"]
+    xs2, w2 = inputs.lasso_batch(D, n, m, 1 - c["rho"], c["sig_s"],
+                                 c["sig_w"], seed=1)
+    xs2 = torch.from_numpy(xs2).to(dev, torch.float32)
+    w2 = torch.from_numpy(w2).to(dev, torch.float32)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    sq = torch.zeros(L + 1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for c0 in range(0, D, 4000):
+        c1 = min(D, c0 + 4000)
+        Q = torch.randn((c1 - c0, m, n), generator=g, device=dev) / np.sqrt(m)
+        xstar = xs2[c0:c1]
+        y = torch.bmm(Q, xstar.unsqueeze(2)).squeeze(2) + w2[c0:c1]
+        x = torch.zeros_like(xstar)
+        sq[0] += (x - xstar).double().pow(2).sum()
+        for t in range(L):
+            r = y - torch.bmm(Q, x.unsqueeze(2)).squeeze(2)
+            v = x + c["tau"] * torch.bmm(r.unsqueeze(1), Q).squeeze(1)
+            x = torch.sign(v) * torch.clamp(v.abs() - c["lam"] * c["tau"],
+                                            min=0.0)
+            sq[t + 1] += (x - xstar).double().pow(2).sum()
+        del Q
+    torch.cuda.synchronize()
+    t_dir = time.perf_counter() - t1
+    e_dir = (sq / (D * n)).cpu().numpy()
+    per_trial_hd = elapsed / args.steps / C
+    per_trial_dir = t_dir / D
+    out = {
+        "metric": "lasso ISTA trials/s (HD, lockstep batch)",
+        "value": C * args.steps / elapsed,
+        "unit": "trials/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": c["name"], "n": n, "m": m, "layers": L,
+                   "trials": C, "queries_per_trial": 2 * L},
+        "mse_curve": {"hd": [round(float(v), 6) for v in e_hd],
+                      "direct": [round(float(v), 6) for v in e_dir],
+                      "max_abs_diff": float(np.max(np.abs(e_hd - e_dir))),
+                      "direct_trials": D},
+        "per_trial_ms": {"hd_batched": per_trial_hd * 1e3,
+                         "direct_dense": per_trial_dir * 1e3,
+                         "direct_over_hd": per_trial_dir / per_trial_hd},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of known size (read 1 GiB, write 1 GiB, five
     times) for scaling the PMC byte counters of the panel kernels."""
@@ -770,7 +862,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4",
                     choices=sorted(list(WORKLOADS) +
-                                   ["c3", "c5", "goe", "spectral"]))
+                                   ["c3", "c5", "goe", "spectral", "lasso"]))
     ap.add_argument("--c5-trials", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
@@ -808,6 +900,9 @@ def main():
         return
     if args.workload == "spectral":
         main_spectral(args)
+        return
+    if args.workload == "lasso":
+        main_lasso(args)
         return
     wl = WORKLOADS[args.workload]
     out = run_single(args, wl)

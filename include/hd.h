@@ -366,6 +366,46 @@ int hd_batch_set_stream(hd_batch b, void* stream);
 /* Release the batch after its stream has drained.  NULL is a no-op. */
 int hd_batch_free(hd_batch b);
 
+/* ------------------------------------------------------------------------
+ * Batches of unrolled-ISTA trials on Gaussian matrices (Sec. 2.1).
+ *
+ * count independent trials, each with its own m x n Gaussian Q (entries
+ * N(0, sigma^2), Philox key (seed, trial0 + i)), run the lasso experiment's
+ * dynamics together: the observation y = Q x* + w (one query), then L
+ * layers of eq. (ista) with per-layer step a_t and threshold theta_t,
+ *     x_{t+1} = eta_{theta_t}(x_t + a_t Q'(y - Q x_t))
+ * (two queries each, Algorithm 1).  All trials advance in lockstep, one
+ * query index at a time, so a query costs a handful of launches for the
+ * whole batch; each trial's answers are those of a separate handle with the
+ * same key up to the order of the FP64 partial sums.
+ * ------------------------------------------------------------------------ */
+typedef struct hd_ista_ctx* hd_ista;
+
+/* Allocate the device state of `count` trials (one arena: per trial four
+ * panels of L + 1 or L columns, FP64 scalars, work vectors) on `stream`.
+ * Requires L + 1 <= n and L <= m (Algorithm 1's capacity), sigma > 0.
+ * Errors: HD_ERR_INVALID, HD_ERR_NOMEM (also beyond 250 GB), HD_ERR_HIP. */
+int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
+                 int32_t count, uint32_t seed, uint32_t trial0, double sigma,
+                 void* stream, hd_ista* out);
+
+/* Run every trial from fresh matrices (the same keys at every call).
+ * a, theta: host arrays of L floats.  xstar: device count x n (x* of trial
+ * i in row i), noise: device count x m (w), X: device count x (L + 1) x n
+ * whose row 0 of every trial holds x_1 on entry; rows 1..L receive
+ * x_2..x_{L+1}.  Stream-ordered.  Errors: HD_ERR_INVALID, HD_ERR_HIP. */
+int hd_ista_run(hd_ista b, const float* a, const float* theta,
+                const void* xstar, const void* noise, void* X);
+
+/* Synchronise and report the sticky device flag (as hd_status). */
+int hd_ista_status(hd_ista b);
+
+/* Change the stream of later calls. */
+int hd_ista_set_stream(hd_ista b, void* stream);
+
+/* Release the batch after its stream has drained.  NULL is a no-op. */
+int hd_ista_free(hd_ista b);
+
 /* Message for an HD_* code (static storage). */
 const char* hd_strerror(int code);
 

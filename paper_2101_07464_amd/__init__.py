@@ -354,6 +354,67 @@ class HaarBatch:
                    "hd_batch_set_graph")
 
 
+class IstaBatch:
+    """Independent unrolled-ISTA trials on Gaussian matrices of one shape
+    (``hd_ista_*``): trial i has an m x n Q with N(0, sigma^2) entries keyed
+    (seed, trial0 + i), observes y = Q x* + w and runs L layers
+    x_{t+1} = soft(x_t + a_t Q'(y - Q x_t), theta_t) from x_1 (zeros by
+    default), all trials in lockstep."""
+
+    def __init__(self, m, n, L, count, seed=0, trial0=0, sigma=1.0,
+                 dtype=None, device="cuda:0"):
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        self.m, self.n, self.L, self.count = m, n, L, count
+        self.dtype = dtype
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().hd_ista_init(
+                _storage(dtype), m, n, L, count, seed, trial0, sigma,
+                _stream_ptr(self.device), ctypes.byref(h)), "hd_ista_init")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().hd_ista_free(h)
+            self._h = None
+
+    def run(self, a, theta, xstar, noise, x1=None):
+        """a, theta: L floats; xstar: (count, n), noise: (count, m) device
+        tensors; x1: None (zeros) or (count, n).  Returns X, (count, L+1, n)
+        with X[:, t] = x_{t+1}."""
+        torch = _torch()
+        L = self.L
+        if len(a) != L or len(theta) != L:
+            raise ValueError("one (a, theta) pair per layer")
+        xstar = xstar.to(self.device, self.dtype).contiguous()
+        noise = noise.to(self.device, self.dtype).contiguous()
+        if xstar.shape != (self.count, self.n) or \
+                noise.shape != (self.count, self.m):
+            raise ValueError("xstar must be (count, n), noise (count, m)")
+        X = torch.zeros((self.count, L + 1, self.n), dtype=self.dtype,
+                        device=self.device)
+        if x1 is not None:
+            X[:, 0] = x1
+        af = (ctypes.c_float * L)(*[float(v) for v in a])
+        tf = (ctypes.c_float * L)(*[float(v) for v in theta])
+        Lb = _lib.load()
+        _lib.check(Lb.hd_ista_set_stream(self._h, _stream_ptr(self.device)),
+                   "hd_ista_set_stream")
+        _lib.check(Lb.hd_ista_run(self._h, af, tf,
+                                  ctypes.c_void_p(xstar.data_ptr()),
+                                  ctypes.c_void_p(noise.data_ptr()),
+                                  ctypes.c_void_p(X.data_ptr())),
+                   "hd_ista_run")
+        self._keep = (xstar, noise)
+        return X
+
+    def status(self):
+        return _lib.load().hd_ista_status(self._h)
+
+
 def _lista_function():
     torch = _torch()
 

@@ -39,7 +39,9 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
            "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
-           "hd_noalloc_scratch_bytes", "hd_spectral_power"]
+           "hd_noalloc_scratch_bytes", "hd_spectral_power", "hd_ista_init",
+           "hd_ista_run", "hd_ista_status", "hd_ista_set_stream",
+           "hd_ista_free"]
 
 
 class HDConfig(ctypes.Structure):
@@ -122,6 +124,13 @@ def load():
         "hd_noalloc_scratch_bytes": (i32, [P(HDConfig),
                                            P(ctypes.c_size_t)]),
         "hd_spectral_power": (i32, [vp, i64, vp, vp, i32, dbl, vp, vp]),
+        "hd_ista_init": (i32, [i32, i64, i64, i32, i32, ctypes.c_uint32,
+                               ctypes.c_uint32, dbl, vp, P(vp)]),
+        "hd_ista_run": (i32, [vp, P(ctypes.c_float), P(ctypes.c_float), vp,
+                              vp, vp]),
+        "hd_ista_status": (i32, [vp]),
+        "hd_ista_set_stream": (i32, [vp, vp]),
+        "hd_ista_free": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

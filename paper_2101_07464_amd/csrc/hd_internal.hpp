@@ -303,6 +303,57 @@ int launch_trial_small(int f64, int op, int ntrials, const TrialDev* d,
 int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
                            BatchMap m, hipStream_t s);
 
+// ------------------------------------------------ Gaussian ISTA batches --
+//
+// Independent trials of unrolled ISTA (eq. (ista)) on Gaussian matrices of
+// one shape m x n, all advancing in lockstep, one query index at a time:
+// query 0 observes y = sigma Q x* + w, then every layer is a Q-query and a
+// Q'-query, so the two sides alternate as data and random side
+// (Algorithm 1) and every running trial has the same reflector counts.
+
+// The arguments of one side s (0: R, n rows; 1: L, m rows) of one trial.
+struct IstaSide {
+  TdotArgs td;       // TDOT with the side as data side (V2 = its basis panel)
+  SmallDataArgs sd;  // z = T' w on it
+  PassArgs pd;       // its data pass
+  GinSmallArgs gs;   // the reflector step after its data pass (G = 1 - s)
+  GinPassArgs gp;    // the random pass with the side as random side
+  int nwg;           // workgroups over its rows
+};
+
+struct IstaTrialDev {
+  IstaSide s[2];
+  void* yobs;  // m: the observation y = sigma Q x* + w
+  void* res;   // m: y - Q x_t
+  void* U;     // n: Q'(y - Q x_t) (query output)
+  void* V;     // n: x_t + a_t Q'(y - Q x_t)
+  void* Yq;    // m: Q x_t (query output)
+};
+
+struct IstaStep {
+  int q;             // query index, 0-based
+  int kR, kL;        // reflectors on each side before the query
+  uint32_t step;     // 1-based query index (the Philox step)
+  int last;          // no query follows
+  double a, theta;   // the layer's step and threshold (Q'-queries)
+  int L;             // layers
+  // the caller's arrays, trial i at offset i * (rows): x* (n), w (m) and
+  // the trajectory X ((L + 1) x n, row 0 = x_1 = 0)
+  const void* xstar;
+  const void* noise;
+  void* X;
+};
+
+// Phases of one query for all trials; each returns 0 or a HIP error.
+int launch_ista_tdot(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s);
+int launch_ista_small(int f64, int phase, int side, int ntrials,
+                      const IstaTrialDev* d, IstaStep st, hipStream_t s);
+int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s);
+int launch_ista_rand(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s);
+
 // Device-to-device copies of 4-byte words, one workgroup per job.// Device-to-device copies of 4-byte words, one workgroup per job.
 struct CopyJob {
   const void* src;

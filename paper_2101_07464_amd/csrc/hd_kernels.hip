@@ -1156,6 +1156,142 @@ __global__ __launch_bounds__(kWG) void k_trial_small(const TrialDev* D,
   }
 }
 
+// ------------------------------------------------ Gaussian ISTA batches --
+//
+// One query of every trial of an ISTA batch (all trials in lockstep, one
+// chunk of 256 rows per workgroup).  The data side ds is R for Q-queries
+// (query 0, the observation y = sigma Q x* + w, and the first query of
+// every layer) and L for Q'-queries (the second query of every layer).
+
+// Row r of trial i's trajectory X ((L + 1) x n).
+template <typename T>
+__device__ __forceinline__ T* ista_row(const IstaStep& st, int64_t n,
+                                       int trial, int r) {
+  return (T*)st.X + ((int64_t)trial * (st.L + 1) + r) * n;
+}
+
+template <typename T>
+__device__ __forceinline__ const void* ista_input(const IstaTrialDev& d,
+                                                  int trial, int ds,
+                                                  const IstaStep& st) {
+  const int64_t n = d.s[0].td.n;
+  if (ds == 1) return d.res;
+  if (st.q == 0) return (const T*)st.xstar + (int64_t)trial * n;
+  // query 2t - 1 reads x_t, row t - 1 of X
+  return ista_row<T>(st, n, trial, (st.q - 1) / 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_ista_tdot(const IstaTrialDev* D,
+                                                   int ds, IstaStep st) {
+  const int nwg = D[0].s[ds].nwg;
+  const int trial = blockIdx.x / nwg;
+  const IstaTrialDev& d = D[trial];
+  TdotArgs a = d.s[ds].td;
+  a.ncols = ds == 0 ? st.kR : st.kL;
+  a.ncols2 = ds == 0 ? st.kL : st.kR;
+  a.b = ista_input<T>(d, trial, ds, st);
+  tdot_body<T, 1, false, false>(a, blockIdx.x % nwg);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_ista_data(const IstaTrialDev* D,
+                                                   int ds, IstaStep st) {
+  const int nwg = D[0].s[ds].nwg;
+  const int trial = blockIdx.x / nwg;
+  const IstaTrialDev& d = D[trial];
+  PassArgs a = d.s[ds].pd;
+  const int kD = ds == 0 ? st.kR : st.kL;
+  a.k = kD;
+  a.x = ista_input<T>(d, trial, ds, st);
+  // this side is the random side of the next query except after query 0
+  a.pf = st.q >= 1 && !st.last;
+  a.pf_step = st.step + 1;
+  a.pf_cut = kD;
+  a.cslot = kD > 0 ? a.cslot : -1;
+  pass_body<T, 1, kPassData>(a, blockIdx.x % nwg);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
+                                                   int gs, IstaStep st) {
+  const int nwg = D[0].s[gs].nwg;
+  const int trial = blockIdx.x / nwg;
+  const IstaTrialDev& d = D[trial];
+  GinPassArgs a = d.s[gs].gp;
+  a.k = gs == 0 ? st.kR : st.kL;
+  a.nb = gs == 0 ? st.kL : st.kR;
+  a.h = a.h + a.nb;  // the basis-panel dots follow the reflector dots
+  a.step = st.step;
+  a.dyn.xprev = nullptr;
+  a.dyn.aux = nullptr;
+  if (st.q == 0) {
+    // y = sigma Q x* + w
+    a.y = d.Yq;
+    a.dyn.kind = kDynAxpy;
+    a.dyn.a = -1.0;
+    a.dyn.b = 1.0;
+    a.dyn.x = (const T*)st.noise + (int64_t)trial * d.s[1].td.n;
+    a.dyn.xnext = d.yobs;
+  } else if (gs == 1) {
+    // Q x_t, then y - Q x_t
+    a.y = d.Yq;
+    a.dyn.kind = kDynResidual;
+    a.dyn.x = d.yobs;
+    a.dyn.xnext = d.res;
+  } else {
+    // u_t = Q'(y - Q x_t), v_t = x_t + a_t u_t, x_{t+1} = soft(v_t, theta_t)
+    const int64_t n = d.s[0].td.n;
+    const int t = st.q / 2;  // 1-based layer
+    a.y = d.U;
+    a.dyn.kind = kDynLista;
+    a.dyn.a = st.a;
+    a.dyn.b = st.theta;
+    a.dyn.x = ista_row<T>(st, n, trial, t - 1);
+    a.dyn.xnext = ista_row<T>(st, n, trial, t);
+    a.dyn.aux = d.V;
+  }
+  gin_pass_body<T, 1>(a, blockIdx.x % nwg);
+}
+
+// One workgroup per trial: the fixed-order sums of its partial rows, then
+//   phase 0 (after the TDOT): z = T' w of the data side;
+//   phase 1 (after the data pass): the data reflector's scalars, its T
+//     column and the random side's coefficients (gin_small_body).
+template <typename T, int PHASE>
+__global__ __launch_bounds__(kWG) void k_ista_small(const IstaTrialDev* D,
+                                                    int ds, IstaStep st) {
+  __shared__ double lds[2 * kWG];
+  const IstaTrialDev& d = D[blockIdx.x];
+  const IstaSide& S = d.s[ds];
+  const int kD = ds == 0 ? st.kR : st.kL;
+  const int kG = ds == 0 ? st.kL : st.kR;
+  const TdotArgs& td = S.td;
+  if (PHASE == 0) {
+    double* w = (double*)S.sd.w;
+    wg_reduce(td.partials, td.pstride, S.nwg, 0, kD + kG, w, lds);
+    if (kD > 0) {
+      SmallDataArgs a = S.sd;
+      a.kp = -1;
+      a.k = kD;
+      small_data_body(a);
+    }
+  } else {
+    double* red = S.gs.D.red;
+    const bool pf = st.q >= 1 && !st.last;
+    if (pf) wg_reduce(td.partials, td.pstride, S.nwg, 0, kD + 1, red, lds);
+    if (kD > 0)
+      wg_reduce(td.partials, td.pstride, S.nwg, S.pd.cslot, kD, red, lds);
+    wg_reduce(td.partials, td.pstride, S.nwg, td.extra, kNumExtra, red, lds);
+    GinSmallArgs a = S.gs;
+    a.k = kD;
+    a.l = kG;
+    a.h = a.h + kD;
+    a.cslot = kD > 0 ? S.pd.cslot : -1;
+    gin_small_body<T>(a);
+  }
+}
+
 // ------------------------------------------------- standalone kernels ----
 
 __device__ __forceinline__ int slot_of(const SlotRanges& rg, int b) {
@@ -1437,6 +1573,67 @@ int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
     HD_DISPATCH_SHAPE(sh, K_, dim3(nblk), dim3(kWG), 0, s, d, m);
 #undef K_
   }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_ista_tdot(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_tdot<double>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_tdot<float>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_ista_small(int f64, int phase, int side, int ntrials,
+                      const IstaTrialDev* d, IstaStep st, hipStream_t s) {
+  if (ntrials <= 0) return 0;
+  if (phase == 0) {
+    if (f64)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_small<double, 0>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, side, st);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_small<float, 0>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, side, st);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_small<double, 1>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, side, st);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_small<float, 1>),
+                         dim3(ntrials), dim3(kWG), 0, s, d, side, st);
+  }
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<double>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<float>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_ista_rand(int f64, int side, int nblk, const IstaTrialDev* d,
+                     IstaStep st, hipStream_t s) {
+  if (nblk <= 0) return 0;
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_rand<double>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_rand<float>), dim3(nblk),
+                       dim3(kWG), 0, s, d, side, st);
   HD_CHECK_LAUNCH();
   return 0;
 }

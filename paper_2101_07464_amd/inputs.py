@@ -49,3 +49,17 @@ def ragged_batch(count, n_lo=1000, n_hi=100000, t_lo=10, t_hi=200, seed=0):
     n = np.clip(n, n_lo, n_hi)
     T = g.integers(t_lo, t_hi + 1, size=count).astype(np.int64)
     return n, T
+
+
+def lasso_batch(count, n, m, p_nonzero, sigma_s, sigma_w, seed=0):
+    """Inputs of `count` lasso trials at once: rows of x* (count x n,
+    Bernoulli-Gaussian as sparse_target) and of the noise w (count x m,
+    N(0, sigma_w^2)), drawn from streams of their own (seeded with
+    (seed, 2^32, tag), apart from every per-trial stream)."""
+    def g(tag):
+        return np.random.default_rng(np.random.SeedSequence([seed, 1 << 32,
+                                                             tag]))
+    sup = g(TAG_SUPPORT).random((count, n)) < p_nonzero
+    amp = g(TAG_AMPL).standard_normal((count, n)) * sigma_s
+    w = g(TAG_NOISE).standard_normal((count, m)) * sigma_w
+    return np.where(sup, amp, 0.0), w

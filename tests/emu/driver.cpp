@@ -7,10 +7,15 @@
 //   0 = Q only, 1 = alternating; CPT 0 = the built-in shape, else forced;
 //   X1_FILE holds N values of the storage type.  Writes OUT_PREFIX.X
 //   ((T+1) x N) and OUT_PREFIX.Y (T x N) and prints "rc <code> status <code>".
+// usage: driver ista M N L COUNT SEED TRIAL0 SIGMA A THETA XSTAR NOISE OUT
+//   an FP32 batch of unrolled-ISTA trials with constant (A, THETA); XSTAR
+//   (COUNT x N) and NOISE (COUNT x M) files; writes OUT (COUNT x (L+1) x N).
 #include "hd_api.hip"
 
 #include <cstdio>
 #include <cstdlib>
+#include <string>
+#include <vector>
 
 static void* read_file(const char* path, size_t bytes) {
   void* p = std::malloc(bytes);
@@ -32,7 +37,33 @@ static void write_file(const char* path, const void* p, size_t bytes) {
   std::fclose(f);
 }
 
+static int ista_main(char** argv) {
+  const int64_t m = std::atoll(argv[2]), n = std::atoll(argv[3]);
+  const int L = std::atoi(argv[4]), C = std::atoi(argv[5]);
+  const uint32_t seed = (uint32_t)std::atol(argv[6]);
+  const uint32_t trial0 = (uint32_t)std::atol(argv[7]);
+  const double sigma = std::atof(argv[8]);
+  std::vector<float> a(L, (float)std::atof(argv[9]));
+  std::vector<float> th(L, (float)std::atof(argv[10]));
+  void* xs = read_file(argv[11], 4 * (size_t)C * n);
+  void* w = read_file(argv[12], 4 * (size_t)C * m);
+  const size_t xb = 4 * (size_t)C * (L + 1) * n;
+  void* X = std::calloc(1, xb);
+  hd_ista b = nullptr;
+  int rc = hd_ista_init(HD_F32, m, n, L, C, seed, trial0, sigma, nullptr, &b);
+  if (!rc) rc = hd_ista_run(b, a.data(), th.data(), xs, w, X);
+  const int st = rc ? 0 : hd_ista_status(b);
+  write_file(argv[13], X, xb);
+  std::printf("rc %d status %d\n", rc, st);
+  hd_ista_free(b);
+  std::free(xs);
+  std::free(w);
+  std::free(X);
+  return rc ? 1 : 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 14 && std::string(argv[1]) == "ista") return ista_main(argv);
   if (argc != 14) {
     std::fprintf(stderr, "usage: see the header of driver.cpp\n");
     return 2;

@@ -14,7 +14,8 @@ runs here through exactly the launches hd_run would issue for it (Haar,
 n = 4099, T = 30, FP32, the case of that fault): it must be clean under both
 sanitizers and agree with the FP64 oracle.  A Gaussian trajectory with Q and
 Q' alternating in the four-chunk launch shape covers the other ensemble and
-the row-split column dots.
+the row-split column dots, and a small batch of unrolled-ISTA trials the
+lockstep Gaussian batch.
 """
 import os
 import subprocess
@@ -41,6 +42,7 @@ def driver(tmp_path_factory):
            "-Wno-unused-command-line-argument",
            "-I", os.path.join(EMU, "shim"), "-I", os.path.join(ROOT, "include"),
            "-I", CSRC, "-x", "c++", os.path.join(EMU, "driver.cpp"),
+           "-x", "c++", os.path.join(CSRC, "hd_ista.hip"),
            "-x", "c++", os.path.join(CSRC, "hd_kernels.hip"),
            "-x", "c++", os.path.join(EMU, "emu.cpp"), "-o", out]
     subprocess.run(cmd, check=True)
@@ -99,3 +101,38 @@ def test_gaussian_alternating_four_chunks_emulated(driver, tmp_path):
     eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
     print("emulated Gaussian, four chunks: mode B %.2e" % eb)
     assert eb < 1e-4
+
+
+def test_ista_batch_emulated(driver, tmp_path):
+    """Three lockstep unrolled-ISTA trials (m = 150, n = 300, 4 layers,
+    FP32) against the oracle's single-trial runs with the same keys."""
+    C, n, m, L, seed, trial0 = 3, 300, 150, 4, 5, 10
+    sig = 1.0 / np.sqrt(m)
+    xs = np.stack([inputs.sparse_target(n, 0.8, 2.0, seed=0, trial=i)
+                   for i in range(C)]).astype(np.float32)
+    w = np.stack([inputs.noise(m, 0.1, seed=0, trial=i)
+                  for i in range(C)]).astype(np.float32)
+    xf, wf, out = (str(tmp_path / f) for f in ("xs.bin", "w.bin", "X.bin"))
+    xs.tofile(xf)
+    w.tofile(wf)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([driver, "ista", str(m), str(n), str(L), str(C),
+                        str(seed), str(trial0), "%.17g" % sig, "0.3", "0.6", xf,
+                        wf, out], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
+    X = np.fromfile(out, dtype=np.float32).reshape(C, L + 1, n)
+    worst = 0.0
+    for i in range(C):
+        orc = oracle.HDOracle(oracle.GINIBRE, n, m=m, tmax=2 * L + 1,
+                              seed=seed, trial=trial0 + i, sigma=sig)
+        y = orc.mv(xs[i].astype(np.float64)) + w[i]
+        Xo, _, _ = oracle.lista_forward(orc, np.zeros(n), y, [0.3] * L,
+                                        [0.6] * L)
+        worst = max(worst, max(relerr(a, b) for a, b in zip(X[i][1:],
+                                                            Xo[1:])))
+    print("emulated ISTA batch: %.2e" % worst)
+    assert worst < 1e-4

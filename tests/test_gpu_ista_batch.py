@@ -1,0 +1,130 @@
+"""Lockstep batches of unrolled-ISTA trials on Gaussian matrices (the lasso
+experiment of Sec. 2.1, eq. (ista); hd_ista_* / IstaBatch) on the GPU.
+
+Parity: every layer of every trial against the FP64 oracle running the same
+trial (same key: observation y = Q x* + w, then the layers) -- FP64 storage
+1e-11, FP32 1e-4 -- and against a separate handle with the same key.
+
+Law (Theorem 1): the experiment of the paper's first figure, n = 1000,
+m = n/2, Q_ij ~ N(0, 1/m), T = 50, lambda = 2, tau = 0.3, rho = 0.2 (the
+probability of a zero in x*), sigma_s = 2, sigma_w = 0.1.  The mean squared
+error e(t) = ||x_t - x*||^2 / n over 20000 HD trials and over 20000 trials of
+the direct method (dense Gaussian Q drawn first, the same iteration with
+dense products on the GPU) must agree at every t: Welch two-sample z below
+4.5 (51 comparisons; under equality of the laws a larger one has
+probability ~3e-4), and two-sample KS on the final error at 1e-3.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2101_07464_amd as hd  # noqa: E402
+from paper_2101_07464_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LAM, TAU, RHO, SIG_S, SIG_W = 2.0, 0.3, 0.2, 2.0, 0.1
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11),
+                                       (torch.float32, 1e-4)])
+def test_ista_batch_matches_oracle(dtype, tol):
+    C, n, L, seed, trial0 = 6, 1000, 12, 3, 100
+    m = n // 2
+    sig = 1.0 / np.sqrt(m)
+    xs, w = inputs.lasso_batch(C, n, m, 1 - RHO, SIG_S, SIG_W, seed=seed)
+    xs = torch.from_numpy(xs).to(DEV, dtype)
+    w = torch.from_numpy(w).to(DEV, dtype)
+    # the layer parameters cross the boundary as FP32 values: the oracle
+    # takes the same values
+    a = [float(np.float32(TAU))] * L
+    th = [float(np.float32(LAM * TAU))] * L
+    B = hd.IstaBatch(m, n, L, C, seed=seed, trial0=trial0, sigma=sig,
+                     dtype=dtype, device=DEV)
+    X = B.run(a, th, xs, w)
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    X = X.double().cpu().numpy()
+    xh, wh = xs.double().cpu().numpy(), w.double().cpu().numpy()
+    worst = 0.0
+    for i in range(C):
+        orc = oracle.HDOracle(oracle.GINIBRE, n, m=m, tmax=2 * L + 1,
+                              seed=seed, trial=trial0 + i, sigma=sig)
+        y = orc.mv(xh[i]) + wh[i]
+        Xo, _, _ = oracle.lista_forward(orc, np.zeros(n), y, a, th)
+        worst = max(worst, max(relerr(p, q) for p, q in zip(X[i][1:],
+                                                            Xo[1:])))
+    print("ISTA batch %s: worst layer error %.2e" % (dtype, worst))
+    assert worst < tol
+    # trial 4 as a separate handle with the same key
+    A = hd.LazyMatrix(hd.GINIBRE, n, m=m, t_max=2 * L + 1, seed=seed,
+                      trial=trial0 + 4, sigma=sig, dtype=dtype, device=DEV)
+    y = A.mv(xs[4]) + w[4]
+    Xs, _, _ = A.lista_forward(a, th, torch.zeros(n, dtype=dtype,
+                                                  device=DEV), y)
+    e = relerr(Xs.double().cpu().numpy()[1:], X[4][1:])
+    print("  batch vs separate handle: %.2e" % e)
+    assert e < tol
+
+
+def _direct_mse(xs, w, L, generator):
+    """The direct method on the GPU: dense m x n Gaussian Q (N(0, 1/m)) per
+    trial drawn first, then the same ISTA iteration with dense products;
+    per-trial ||x_t - x*||^2 / n for t = 1..L+1."""
+    C, n = xs.shape
+    m = w.shape[1]
+    out = torch.empty((C, L + 1), dtype=torch.float64, device=DEV)
+    for c0 in range(0, C, 4000):
+        c1 = min(C, c0 + 4000)
+        Q = torch.randn((c1 - c0, m, n), generator=generator, device=DEV)
+        Q /= np.sqrt(m)
+        x_star = xs[c0:c1]
+        y = torch.bmm(Q, x_star.unsqueeze(2)).squeeze(2) + w[c0:c1]
+        x = torch.zeros_like(x_star)
+        out[c0:c1, 0] = (x - x_star).double().pow(2).sum(1) / n
+        for t in range(L):
+            r = y - torch.bmm(Q, x.unsqueeze(2)).squeeze(2)
+            u = torch.bmm(r.unsqueeze(1), Q).squeeze(1)   # Q' r
+            v = x + TAU * u
+            x = torch.sign(v) * torch.clamp(v.abs() - LAM * TAU, min=0.0)
+            out[c0:c1, t + 1] = (x - x_star).double().pow(2).sum(1) / n
+        del Q
+    return out.cpu().numpy()
+
+
+def test_lasso_mse_matches_direct_method():
+    C, n, L = 20000, 1000, 50
+    m = n // 2
+    sig = 1.0 / np.sqrt(m)
+    xs_h, w_h = inputs.lasso_batch(C, n, m, 1 - RHO, SIG_S, SIG_W, seed=11)
+    xs = torch.from_numpy(xs_h).to(DEV, torch.float32)
+    w = torch.from_numpy(w_h).to(DEV, torch.float32)
+    B = hd.IstaBatch(m, n, L, C, seed=11, trial0=0, sigma=sig, device=DEV)
+    X = B.run([TAU] * L, [LAM * TAU] * L, xs, w)
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    e_hd = ((X - xs.unsqueeze(1)).double().pow(2).sum(2) / n).cpu().numpy()
+    del X, B
+    torch.cuda.empty_cache()
+    # the direct method on independent inputs of the same law
+    xs2_h, w2_h = inputs.lasso_batch(C, n, m, 1 - RHO, SIG_S, SIG_W, seed=12)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(12)
+    e_dir = _direct_mse(torch.from_numpy(xs2_h).to(DEV, torch.float32),
+                        torch.from_numpy(w2_h).to(DEV, torch.float32), L, g)
+    mh, md = e_hd.mean(0), e_dir.mean(0)
+    se = np.sqrt(e_hd.var(0, ddof=1) / C + e_dir.var(0, ddof=1) / C)
+    z = np.abs(mh - md) / se
+    ks = stats.ks_2samp(e_hd[:, -1], e_dir[:, -1]).pvalue
+    print("lasso MSE: HD e(T) %.5f direct %.5f; max |z| %.2f at t=%d; "
+          "KS p %.3f" % (mh[-1], md[-1], z.max(), int(z.argmax()) + 1, ks))
+    assert mh[-1] < 0.85 * mh[0]         # ISTA reduces the error
+    assert z.max() < 4.5
+    assert ks > 1e-3
