@@ -52,6 +52,23 @@ def lib():
         L.hdo_normals.restype = None
         L.hdo_apply_householder.argtypes = [vp, i64, vp, vp, i32]
         L.hdo_apply_householder.restype = i32
+        # complex HD (hd_cplx_oracle.c)
+        L.hdoc_normals.argtypes = [u32, u32, u32, u32, i64, i64, vp]
+        L.hdoc_normals.restype = None
+        L.hdoc_apply_householder.argtypes = [vp, i64, vp, i32, vp]
+        L.hdoc_apply_householder.restype = i32
+        L.hdoc_new.restype = vp
+        L.hdoc_new.argtypes = [i32, i64, i64, i32, u32, u32, dbl]
+        L.hdoc_delete.argtypes = [vp]
+        L.hdoc_delete.restype = None
+        L.hdoc_query.argtypes = [vp, i32, vp, vp]
+        L.hdoc_query.restype = i32
+        L.hdoc_counts.argtypes = [vp, vp, vp, vp]
+        L.hdoc_counts.restype = None
+        L.hdoc_reflector.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.hdoc_reflector.restype = i32
+        L.hdoc_basis.argtypes = [vp, i32, vp, vp]
+        L.hdoc_basis.restype = i32
         _LIB = L
     return _LIB
 
@@ -162,6 +179,125 @@ class HDOracle:
         if lib().hdo_basis(self._h, step1, _ptr(u), _ptr(v)) != 0:
             raise IndexError(step1)
         return u, v
+
+
+# ---------------------------------------------------------------------
+# Complex HD (Sec. 3.4): complex Ginibre and the unitary group U(n).
+# ---------------------------------------------------------------------
+
+def cnormals(seed, trial, step, tag, i0, count):
+    """Complex normals i0..i0+count-1: (N_2i + i N_2i+1) / sqrt(2) from the
+    real stream (seed, trial, step, tag)."""
+    out = np.empty(int(count), dtype=np.complex128)
+    if count:
+        lib().hdoc_normals(seed, trial, step, tag, int(i0), int(count),
+                           _ptr(out))
+    return out
+
+
+def capply_householder(v, z, adjoint=False):
+    """H(v) z (or H(v)^H z) with the unitary reflector of eq.
+    (Householder_c); returns (result, is_identity)."""
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    out = np.empty_like(z)
+    ident = lib().hdoc_apply_householder(_ptr(v), v.size, _ptr(z),
+                                         int(bool(adjoint)), _ptr(out))
+    if ident < 0:
+        raise MemoryError
+    return out, bool(ident)
+
+
+class CHDOracle:
+    """Lazy complex random matrix Q (complex Ginibre, E|Q_ij|^2 = sigma^2, or
+    Haar on U(n)) answering y = Q x and y = Q^H x."""
+
+    def __init__(self, ensemble, n, m=None, tmax=None, seed=0, trial=0,
+                 sigma=1.0):
+        m = n if m is None else m
+        if tmax is None:
+            tmax = min(m, n)
+        self.ensemble, self.m, self.n, self.tmax = ensemble, m, n, tmax
+        self.seed, self.trial, self.sigma = seed, trial, sigma
+        self._h = lib().hdoc_new(ensemble, m, n, tmax, seed, trial, sigma)
+        if not self._h:
+            raise ValueError("invalid oracle configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().hdoc_delete(h)
+            self._h = None
+
+    def query(self, x, adjoint=False):
+        din, dout = (self.m, self.n) if adjoint else (self.n, self.m)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        if x.shape != (din,):
+            raise ValueError("x has shape %s, expected (%d,)" % (x.shape, din))
+        y = np.empty(dout, dtype=np.complex128)
+        rc = lib().hdoc_query(self._h, int(bool(adjoint)), _ptr(x), _ptr(y))
+        if rc == -2:
+            raise OverflowError("HD capacity exhausted")
+        if rc != 0:
+            raise MemoryError
+        return y
+
+    def mv(self, x):
+        return self.query(x, False)
+
+    def rmv(self, x):
+        return self.query(x, True)
+
+    def counts(self):
+        t, r, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lib().hdoc_counts(self._h, ctypes.byref(t), ctypes.byref(r),
+                          ctypes.byref(l))
+        return t.value, r.value, l.value
+
+    def reflector(self, side, index1):
+        """Reflector `index1` (1-based) of a side: dict with k, w (length
+        dim - k + 1), r, theta, nu, pivot, ident."""
+        dim = self.n if side == SIDE_R else self.m
+        w = np.zeros(dim - index1 + 1, dtype=np.complex128)
+        r, th, nu = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        piv = np.zeros(1, dtype=np.complex128)
+        ident = ctypes.c_int()
+        rc = lib().hdoc_reflector(self._h, side, index1, _ptr(w),
+                                  ctypes.byref(r), ctypes.byref(th),
+                                  ctypes.byref(nu), _ptr(piv),
+                                  ctypes.byref(ident))
+        if rc != 0:
+            raise IndexError(index1)
+        return dict(k=index1, w=w, r=r.value, theta=th.value, nu=nu.value,
+                    pivot=complex(piv[0]), ident=bool(ident.value))
+
+    def basis(self, step1):
+        u = np.empty(self.m, dtype=np.complex128)
+        v = np.empty(self.n, dtype=np.complex128)
+        if lib().hdoc_basis(self._h, step1, _ptr(u), _ptr(v)) != 0:
+            raise IndexError(step1)
+        return u, v
+
+
+def f_ctanh(y, x_t, a, b):
+    """Complex map x_{t+1} = tanh(a |y|) e^{i arg y} + b x_t (0 where y = 0),
+    the complex workload's stand-in for the real tanh map."""
+    mag = np.abs(y)
+    ph = np.where(mag > 0, y / np.where(mag > 0, mag, 1.0), 0.0)
+    return np.tanh(a * mag) * ph + b * x_t
+
+
+def run_ctrajectory(orc, x1, T, a, b, pattern="Q"):
+    """Free-running complex trajectory: X (T+1 rows) and Y (T rows);
+    pattern "Q" or "alt" (Q, Q^H, Q, ...; square Q only)."""
+    X = [np.asarray(x1, dtype=np.complex128)]
+    Y = []
+    for t in range(T):
+        adj = pattern == "alt" and t % 2 == 1
+        y = orc.query(X[-1], adj)
+        Y.append(y)
+        X.append(f_ctanh(y, X[-1], a, b))
+    return np.array(X), np.array(Y)
 
 
 # ---------------------------------------------------------------------

@@ -8,14 +8,15 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "hd_oracle.c")
+SRCS = [os.path.join(HERE, "hd_oracle.c"),
+        os.path.join(HERE, "hd_cplx_oracle.c")]
 LIB = os.path.join(HERE, "liboracle_hd.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", tmp, SRC, "-lm"]
+           "-o", tmp] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
