@@ -647,6 +647,97 @@ def main_lasso(args):
     print(json.dumps(out), flush=True)
 
 
+CPLX = dict(name="unitary_haar_n1e7_T200_ctanh_c64", n=10_000_000, T=200,
+            a=1.0, b=0.1, modeb=4)
+CPLX_KINDS = {0: "k_cx_dots (L1: data dots | random draw dots)",
+              1: "k_cx_pass<data> (data pass)",
+              2: "k_cx_pass<haar out> (output pass, map fused)"}
+
+
+def main_cplx(args):
+    """Complex HD (Sec. 3.4) on the unitary group: one trial of T = 200
+    queries y_t = Q x_t, Q Haar on U(1e7), x_{t+1} = tanh(|y_t|) e^{i arg y_t}
+    + 0.1 x_t, complex64 storage (the complex counterpart of the large single
+    trial).  A step is one whole trajectory from a fresh Q (hd_creset)."""
+    import torch
+    import oracle
+    import paper_2101_07464_amd as hd
+    from paper_2101_07464_amd import inputs
+    dev = "cuda:0"
+    c = CPLX
+    n, T = c["n"], c["T"]
+    x1 = torch.from_numpy(inputs.cx1_normal(n, seed=0)).to(dev,
+                                                          torch.complex64)
+    A = hd.CLazyMatrix(hd.HAAR, n, t_max=T, seed=0, dtype=torch.complex64,
+                       device=dev)
+
+    def step(i, record=False):
+        A.reset(0, i)
+        return A.run(x1, T, c["a"], c["b"], record=record)
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if A.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    A.profile(True)
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    kinds = {k: A.profile_read(k) for k in (0, 1, 2)}
+    A.profile(False)
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, launches, nbytes = kinds[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    W = nominal_work(n, T)
+    per_kernel = {CPLX_KINDS[k]: {
+        "avg_launch_us": v[0] * 1e3 / max(v[1], 1),
+        "frac": (v[2] / (v[0] * 1e-3) / 1e9 / HBM_PEAK_GBS) if v[0] else 0.0}
+        for k, v in kinds.items()}
+    out = {
+        "metric": METRIC, "value": W * args.steps / elapsed,
+        "unit": "elem-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": c["name"], "ensemble": "haar_unitary",
+                   "n": n, "T": T, "pattern": "Q",
+                   "dynamics": "tanh(|y|) e^{i arg y} + 0.1 x",
+                   "elem_updates_per_step": W},
+        "roofline": {"bound": "hbm", "kernel": CPLX_KINDS[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": launches,
+                     "avg_launch_us": ms * 1e3 / max(launches, 1),
+                     "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
+                     "per_kernel": per_kernel},
+    }
+    if not args.no_checks:
+        X, Y = step(0, record=True)
+        torch.cuda.synchronize()
+        xn = torch.linalg.vector_norm(X[:T].to(torch.complex128), dim=1)
+        yn = torch.linalg.vector_norm(Y.to(torch.complex128), dim=1)
+        iso = float(((yn / xn) - 1).abs().max())
+        q = c["modeb"]
+        orc = oracle.CHDOracle(oracle.HAAR, n, tmax=T, seed=0, trial=0)
+        Xh = X[:q].to(torch.complex128).cpu().numpy()
+        Yh = Y[:q].to(torch.complex128).cpu().numpy()
+        eb = max(float(np.abs(orc.mv(Xh[t]) - Yh[t]).max() /
+                       np.abs(Yh[t]).max()) for t in range(q))
+        out["accuracy"] = {
+            "oracle_replay": {"queries": q, "max_rel_err": eb,
+                              "tolerance": 1e-4},
+            "unitary_isometry": {"answers": T, "max_err": iso,
+                                 "what": "max_t | ||y_t|| / ||x_t|| - 1 |"}}
+        del X, Y
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of known size (read 1 GiB, write 1 GiB, five
     times) for scaling the PMC byte counters of the panel kernels."""
@@ -862,7 +953,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4",
                     choices=sorted(list(WORKLOADS) +
-                                   ["c3", "c5", "goe", "spectral", "lasso"]))
+                                   ["c3", "c5", "goe", "spectral", "lasso",
+                                    "cplx"]))
     ap.add_argument("--c5-trials", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the plain copy used to scale PMC bytes")
@@ -903,6 +995,9 @@ def main():
         return
     if args.workload == "lasso":
         main_lasso(args)
+        return
+    if args.workload == "cplx":
+        main_cplx(args)
         return
     wl = WORKLOADS[args.workload]
     out = run_single(args, wl)

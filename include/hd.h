@@ -406,6 +406,87 @@ int hd_ista_set_stream(hd_ista b, void* stream);
 /* Release the batch after its stream has drained.  NULL is a no-op. */
 int hd_ista_free(hd_ista b);
 
+/* ------------------------------------------------------------------------
+ * Complex HD (Sec. 3.4): the complex Ginibre ensemble (entries with
+ * E|Q_ij|^2 = sigma^2, real and imaginary parts N(0, sigma^2 / 2)), the
+ * Haar ensemble on the unitary group U(n), and the Gaussian unitary ensemble
+ * G = (Q + Q^H) / sqrt(2) as two queries on a square complex Ginibre handle.
+ * Reflectors are the unitary reflectors of eq. (Householder_c); Algorithms
+ * 1 and 2 run with the conjugate transpose in place of the transpose, and
+ * where the real algorithms apply a (symmetric) reflector to build an output
+ * or an output-space basis vector, the conjugate transpose of the unitary
+ * one is applied: Haar y = Q x is L_1^H .. L_t^H R_t p_t; Ginibre
+ * u_t = L_1^H .. L_l^H Z_{1:l} g_t, v_t = R_1^H .. R_r^H e_r, y = sigma
+ * sum_i (v_i^H x) u_i (and the mirror images for y = Q^H x).
+ *
+ * Vectors are device arrays of interleaved (re, im) pairs in the storage
+ * type (HD_F32: complex float, HD_F64: complex double); scalars, reflector
+ * norms and phases, T factors and the phase prefix are FP64.  Complex normal
+ * i of query t is (N_2i + i N_2i+1) / sqrt(2) from the real stream of the
+ * header's draws (key (seed, trial), step t, tag 0).  Launches are ordered
+ * on the handle's stream; calls on one handle must not overlap.
+ * ------------------------------------------------------------------------ */
+typedef struct hd_cctx* hd_chandle;
+
+/* Allocate a complex handle: ensemble HD_GINIBRE (m x n) or HD_HAAR (m == n),
+ * at most t_max <= 1024 queries (Haar: t_max <= n; Ginibre: at most n
+ * Q-queries and m Q^H-queries), panels of t_max + 1 columns per side (plus
+ * basis panels on Ginibre).  sigma: entry scale of Ginibre (ignored on Haar).
+ * Errors: HD_ERR_INVALID (bad configuration, out == NULL), HD_ERR_NOMEM,
+ * HD_ERR_HIP. */
+int hd_cinit(int32_t ensemble, int32_t storage, int64_t m, int64_t n,
+             int32_t t_max, uint32_t seed, uint32_t trial, double sigma,
+             void* stream, hd_chandle* out);
+
+/* One query: y = Q x (adjoint = 0; x of length n, y of length m) or
+ * y = Q^H x (adjoint != 0).  x and y must not alias.  Errors:
+ * HD_ERR_INVALID, HD_ERR_CAPACITY (state unchanged), HD_ERR_HIP. */
+int hd_cstep(hd_chandle h, int32_t adjoint, const void* x, void* y);
+
+/* T queries y_t = Q x_t on a Haar handle with the fused map
+ * x_{t+1} = tanh(a |y_t|) e^{i arg y_t} + b x_t (entrywise; 0 where y = 0).
+ * X: device (T + 1) x n, row 0 = x_1 on entry, rows 1..T receive
+ * x_2..x_{T+1}; Y: NULL or device T x n for the answers.  Errors:
+ * HD_ERR_INVALID, HD_ERR_UNSUPPORTED (not a Haar handle), HD_ERR_CAPACITY
+ * (checked before any query), HD_ERR_HIP. */
+int hd_crun(hd_chandle h, int32_t T, double a, double b, void* X, void* Y);
+
+/* GUE: y = G x with G = (Q + Q^H) / sqrt(2) on a square complex Ginibre
+ * handle (two queries, the second combining the first answer; entries of G
+ * have E|G_ij|^2 = sigma^2, the diagonal real).  The first answer is staged
+ * in a buffer allocated on first use.  Errors: HD_ERR_INVALID (not a square
+ * Ginibre handle, null or aliased pointers), HD_ERR_CAPACITY, HD_ERR_NOMEM,
+ * HD_ERR_HIP. */
+int hd_cgue_step(hd_chandle h, const void* x, void* y);
+
+/* Start a fresh matrix with key (seed, trial) on the same allocation (the
+ * sticky flag is cleared too).  Stream-ordered.  Errors: HD_ERR_INVALID,
+ * HD_ERR_HIP. */
+int hd_creset(hd_chandle h, uint32_t seed, uint32_t trial);
+
+/* Queries so far and the reflector counts |R|, |L|. */
+int hd_ccounts(hd_chandle h, int32_t* t, int32_t* r, int32_t* l);
+
+/* Synchronise the stream; HD_OK, HD_ERR_NONFINITE (a reflector norm was not
+ * finite since the last reset) or HD_ERR_HIP. */
+int hd_cstatus(hd_chandle h);
+
+/* Change the stream of later calls. */
+int hd_cset_stream(hd_chandle h, void* stream);
+
+/* Timing of the complex panel launches with events recorded by the
+ * dispatches on the handle's stream: hd_cprofile(h, 1) starts recording
+ * (clears earlier records), 0 stops; hd_cprofile_read gives, for one kind
+ * (0 = dots of L1, 1 = data pass, 2 = output pass), the summed durations,
+ * the launch count and the algorithmic bytes (every panel column once, the
+ * vectors read and written).  Both synchronise the stream. */
+int hd_cprofile(hd_chandle h, int32_t enable);
+int hd_cprofile_read(hd_chandle h, int32_t kind, double* ms,
+                     int64_t* launches, double* bytes);
+
+/* Release the handle after its stream has drained.  NULL is a no-op. */
+int hd_cfree(hd_chandle h);
+
 /* Message for an HD_* code (static storage). */
 const char* hd_strerror(int code);
 

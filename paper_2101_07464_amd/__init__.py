@@ -547,3 +547,120 @@ def usv_mv(U, V, s, x, transpose=False):
         ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
         "hd_usv_step")
     return y
+
+
+class CLazyMatrix:
+    """Lazy complex m x n random matrix on one GPU (``hd_c*``, Sec. 3.4).
+
+    ensemble: GINIBRE (complex Gaussian entries, E|Q_ij|^2 = sigma^2) or HAAR
+    (the unitary group U(n), m = n).  dtype: torch.complex64 or
+    torch.complex128 (panel and vector storage).  ``mv``/``rmv`` answer
+    Q x and Q^H x; ``gue_mv`` answers G x for G = (Q + Q^H) / sqrt(2) on a
+    square Ginibre handle; ``run`` runs the fused Haar trajectory."""
+
+    def __init__(self, ensemble, n, m=None, t_max=None, seed=0, trial=0,
+                 sigma=1.0, dtype=None, device="cuda:0"):
+        torch = _torch()
+        dtype = torch.complex64 if dtype is None else dtype
+        if dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("dtype must be complex64 or complex128")
+        m = n if m is None else m
+        t_max = min(m, n, 1024) if t_max is None else t_max
+        self.ensemble, self.m, self.n, self.t_max = ensemble, m, n, t_max
+        self.dtype = dtype
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().hd_cinit(
+                ensemble, HD_F64 if dtype == torch.complex128 else HD_F32, m,
+                n, t_max, seed, trial, sigma, _stream_ptr(self.device),
+                ctypes.byref(h)), "hd_cinit")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().hd_cfree(h)
+            self._h = None
+
+    def _sync_stream(self):
+        _lib.check(_lib.load().hd_cset_stream(self._h,
+                                              _stream_ptr(self.device)),
+                   "hd_cset_stream")
+
+    def _vec(self, x, n):
+        x = x.to(self.device, self.dtype).contiguous()
+        if x.shape != (n,):
+            raise ValueError("expected a vector of length %d" % n)
+        return x
+
+    def query(self, x, adjoint=False):
+        torch = _torch()
+        x = self._vec(x, self.m if adjoint else self.n)
+        y = torch.empty(self.n if adjoint else self.m, dtype=self.dtype,
+                        device=self.device)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_cstep(self._h, 1 if adjoint else 0,
+                                        ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr())),
+                   "hd_cstep")
+        return y
+
+    def mv(self, x):
+        return self.query(x, False)
+
+    def rmv(self, x):
+        return self.query(x, True)
+
+    def gue_mv(self, x):
+        torch = _torch()
+        x = self._vec(x, self.n)
+        y = torch.empty(self.n, dtype=self.dtype, device=self.device)
+        self._sync_stream()
+        _lib.check(_lib.load().hd_cgue_step(self._h,
+                                            ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(y.data_ptr())),
+                   "hd_cgue_step")
+        return y
+
+    def run(self, x1, T, a, b, record=True):
+        """T queries y_t = Q x_t with x_{t+1} = tanh(a |y_t|) e^{i arg y_t}
+        + b x_t (Haar).  Returns X ((T+1) x n) and Y (T x n, or None)."""
+        torch = _torch()
+        X = torch.empty((T + 1, self.n), dtype=self.dtype, device=self.device)
+        X[0] = self._vec(x1, self.n)
+        Y = torch.empty((T, self.n), dtype=self.dtype,
+                        device=self.device) if record else None
+        self._sync_stream()
+        _lib.check(_lib.load().hd_crun(
+            self._h, T, float(a), float(b), ctypes.c_void_p(X.data_ptr()),
+            ctypes.c_void_p(Y.data_ptr()) if record else None), "hd_crun")
+        return X, Y
+
+    def reset(self, seed, trial=0):
+        self._sync_stream()
+        _lib.check(_lib.load().hd_creset(self._h, seed, trial), "hd_creset")
+
+    def counts(self):
+        t, r, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.load().hd_ccounts(self._h, ctypes.byref(t),
+                                          ctypes.byref(r), ctypes.byref(l)),
+                   "hd_ccounts")
+        return t.value, r.value, l.value
+
+    def status(self):
+        return _lib.load().hd_cstatus(self._h)
+
+    def profile(self, enable):
+        self._sync_stream()
+        _lib.check(_lib.load().hd_cprofile(self._h, 1 if enable else 0),
+                   "hd_cprofile")
+
+    def profile_read(self, kind):
+        """(ms, launches, algorithmic bytes) of kind 0 (L1 dots), 1 (data
+        pass) or 2 (output pass) since profiling started."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _lib.check(_lib.load().hd_cprofile_read(
+            self._h, kind, ctypes.byref(ms), ctypes.byref(n),
+            ctypes.byref(by)), "hd_cprofile_read")
+        return ms.value, n.value, by.value

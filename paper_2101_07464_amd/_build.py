@@ -12,7 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhd.so")
-SOURCES = ["hd_api.hip", "hd_batch.hip", "hd_ista.hip", "hd_kernels.hip"]
+SOURCES = ["hd_api.hip", "hd_batch.hip", "hd_ista.hip", "hd_kernels.hip",
+           "hd_cplx.hip"]
 ARCH = "gfx950"
 
 

@@ -41,7 +41,9 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
            "hd_noalloc_scratch_bytes", "hd_spectral_power", "hd_ista_init",
            "hd_ista_run", "hd_ista_status", "hd_ista_set_stream",
-           "hd_ista_free"]
+           "hd_ista_free", "hd_cinit", "hd_cstep", "hd_crun",
+           "hd_cgue_step", "hd_creset", "hd_ccounts", "hd_cstatus",
+           "hd_cset_stream", "hd_cfree", "hd_cprofile", "hd_cprofile_read"]
 
 
 class HDConfig(ctypes.Structure):
@@ -131,6 +133,19 @@ def load():
         "hd_ista_status": (i32, [vp]),
         "hd_ista_set_stream": (i32, [vp, vp]),
         "hd_ista_free": (i32, [vp]),
+        "hd_cinit": (i32, [i32, i32, i64, i64, i32, ctypes.c_uint32,
+                           ctypes.c_uint32, ctypes.c_double, vp,
+                           P(vp)]),
+        "hd_cstep": (i32, [vp, i32, vp, vp]),
+        "hd_crun": (i32, [vp, i32, ctypes.c_double, ctypes.c_double, vp, vp]),
+        "hd_cgue_step": (i32, [vp, vp, vp]),
+        "hd_creset": (i32, [vp, ctypes.c_uint32, ctypes.c_uint32]),
+        "hd_ccounts": (i32, [vp, P(i32), P(i32), P(i32)]),
+        "hd_cstatus": (i32, [vp]),
+        "hd_cset_stream": (i32, [vp, vp]),
+        "hd_cfree": (i32, [vp]),
+        "hd_cprofile": (i32, [vp, i32]),
+        "hd_cprofile_read": (i32, [vp, i32, P(dbl), P(i64), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -28,6 +28,13 @@ def x1_normal(n, seed=0, trial=0, scale=None):
     return rng(seed, trial, TAG_X1).standard_normal(n) * s
 
 
+def cx1_normal(n, seed=0, trial=0):
+    """Complex x_1 with i.i.d. circular entries, E|x_i|^2 = 1 (real and
+    imaginary parts N(0, 1/2))."""
+    g = rng(seed, trial, TAG_X1).standard_normal((2, n))
+    return (g[0] + 1j * g[1]) / np.sqrt(2.0)
+
+
 def sparse_target(n, p_nonzero, sigma_s, seed=0, trial=0):
     """Bernoulli-Gaussian vector: entry nonzero with probability p_nonzero,
     nonzero entries N(0, sigma_s^2) (the prior of the lasso example)."""

@@ -10,10 +10,17 @@
 // usage: driver ista M N L COUNT SEED TRIAL0 SIGMA A THETA XSTAR NOISE OUT
 //   an FP32 batch of unrolled-ISTA trials with constant (A, THETA); XSTAR
 //   (COUNT x N) and NOISE (COUNT x M) files; writes OUT (COUNT x (L+1) x N).
+// usage: driver cplx ENS M N F64 SEED TRIAL SIGMA PATTERN X_FILE OUT
+//   complex queries on one handle: PATTERN is a string of Q (y = Q x),
+//   H (y = Q^H x) and G (GUE step); X_FILE holds the query vectors back to
+//   back (interleaved complex, storage type), OUT receives the answers.
+// usage: driver crun N T A B F64 SEED TRIAL X1_FILE OUT_PREFIX
+//   a complex Haar trajectory (hd_crun); writes OUT_PREFIX.X and .Y.
 #include "hd_api.hip"
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -62,8 +69,78 @@ static int ista_main(char** argv) {
   return rc ? 1 : 0;
 }
 
+static int cplx_main(char** argv) {
+  const int ens = std::atoi(argv[2]);
+  const int64_t m = std::atoll(argv[3]), n = std::atoll(argv[4]);
+  const int f64 = std::atoi(argv[5]);
+  const uint32_t seed = (uint32_t)std::atol(argv[6]);
+  const uint32_t trial = (uint32_t)std::atol(argv[7]);
+  const double sigma = std::atof(argv[8]);
+  const std::string pat = argv[9];
+  const size_t es = f64 ? 16 : 8;
+  size_t in = 0, out = 0;
+  int tq = 0;
+  for (char c : pat) {
+    in += es * (c == 'H' ? m : n);
+    out += es * (c == 'Q' ? m : n);
+    tq += c == 'G' ? 2 : 1;
+  }
+  char* X = (char*)read_file(argv[10], in);
+  char* Y = (char*)std::calloc(1, out);
+  hd_chandle h = nullptr;
+  int rc = hd_cinit(ens, f64 ? HD_F64 : HD_F32, m, n, tq, seed, trial, sigma,
+                    nullptr, &h);
+  size_t xi = 0, yi = 0;
+  for (char c : pat) {
+    if (rc) break;
+    if (c == 'G')
+      rc = hd_cgue_step(h, X + xi, Y + yi);
+    else
+      rc = hd_cstep(h, c == 'H', X + xi, Y + yi);
+    xi += es * (c == 'H' ? m : n);
+    yi += es * (c == 'Q' ? m : n);
+  }
+  const int st = rc ? 0 : hd_cstatus(h);
+  write_file(argv[11], Y, out);
+  std::printf("rc %d status %d\n", rc, st);
+  hd_cfree(h);
+  std::free(X);
+  std::free(Y);
+  return rc ? 1 : 0;
+}
+
+static int crun_main(char** argv) {
+  const int64_t n = std::atoll(argv[2]);
+  const int T = std::atoi(argv[3]);
+  const double a = std::atof(argv[4]), b = std::atof(argv[5]);
+  const int f64 = std::atoi(argv[6]);
+  const uint32_t seed = (uint32_t)std::atol(argv[7]);
+  const uint32_t trial = (uint32_t)std::atol(argv[8]);
+  const size_t row = (f64 ? 16 : 8) * (size_t)n;
+  char* X = (char*)std::calloc(1, row * (T + 1));
+  char* Y = (char*)std::calloc(1, row * T);
+  void* x1 = read_file(argv[9], row);
+  std::memcpy(X, x1, row);
+  hd_chandle h = nullptr;
+  int rc = hd_cinit(HD_HAAR, f64 ? HD_F64 : HD_F32, n, n, T, seed, trial, 1.0,
+                    nullptr, &h);
+  if (!rc) rc = hd_crun(h, T, a, b, X, Y);
+  const int st = rc ? 0 : hd_cstatus(h);
+  const std::string pre = argv[10];
+  write_file((pre + ".X").c_str(), X, row * (T + 1));
+  write_file((pre + ".Y").c_str(), Y, row * T);
+  std::printf("rc %d status %d\n", rc, st);
+  hd_cfree(h);
+  std::free(X);
+  std::free(Y);
+  std::free(x1);
+  return rc ? 1 : 0;
+}
+
 int main(int argc, char** argv) {
   if (argc == 14 && std::string(argv[1]) == "ista") return ista_main(argv);
+  if (argc == 12 && std::string(argv[1]) == "cplx") return cplx_main(argv);
+  if (argc == 11 && std::string(argv[1]) == "crun") return crun_main(argv);
   if (argc != 14) {
     std::fprintf(stderr, "usage: see the header of driver.cpp\n");
     return 2;

@@ -31,6 +31,9 @@ struct alignas(16) float4 {
 struct alignas(16) double2 {
   double x, y;
 };
+struct alignas(8) float2 {
+  float x, y;
+};
 
 struct dim3 {
   unsigned x, y, z;
@@ -116,6 +119,13 @@ int emu_readfirstlane(int v);
 #define __builtin_amdgcn_permlane32_swap emu_permlane32_swap
 #define __builtin_amdgcn_permlane16_swap emu_permlane16_swap
 #define __builtin_amdgcn_readfirstlane emu_readfirstlane
+
+// fibers of a workgroup never interleave inside one call: plain updates
+inline int atomicOr(int* p, int v) {
+  const int o = *p;
+  *p = o | v;
+  return o;
+}
 
 using std::isfinite;
 inline int min(int a, int b) { return a < b ? a : b; }

@@ -15,7 +15,9 @@ n = 4099, T = 30, FP32, the case of that fault): it must be clean under both
 sanitizers and agree with the FP64 oracle.  A Gaussian trajectory with Q and
 Q' alternating in the four-chunk launch shape covers the other ensemble and
 the row-split column dots, and a small batch of unrolled-ISTA trials the
-lockstep Gaussian batch.
+lockstep Gaussian batch.  The complex path (Sec. 3.4) runs mixed Q / Q^H
+sequences with a zero query on U(n) and on a rectangular complex Ginibre
+matrix, GUE steps, and a fused FP32 Haar trajectory.
 """
 import os
 import subprocess
@@ -44,6 +46,7 @@ def driver(tmp_path_factory):
            "-I", CSRC, "-x", "c++", os.path.join(EMU, "driver.cpp"),
            "-x", "c++", os.path.join(CSRC, "hd_ista.hip"),
            "-x", "c++", os.path.join(CSRC, "hd_kernels.hip"),
+           "-x", "c++", os.path.join(CSRC, "hd_cplx.hip"),
            "-x", "c++", os.path.join(EMU, "emu.cpp"), "-o", out]
     subprocess.run(cmd, check=True)
     return out
@@ -136,3 +139,67 @@ def test_ista_batch_emulated(driver, tmp_path):
                                                             Xo[1:])))
     print("emulated ISTA batch: %.2e" % worst)
     assert worst < 1e-4
+
+
+def _crun_queries(driver, tmp_path, ens, m, n, f64, sigma, pattern, xs):
+    dt = np.complex128 if f64 else np.complex64
+    xf, yf = str(tmp_path / "cx.bin"), str(tmp_path / "cy.bin")
+    np.concatenate([x.astype(dt) for x in xs]).tofile(xf)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([driver, "cplx", str(ens), str(m), str(n), str(f64),
+                        "3", "4", "%.17g" % sigma, pattern, xf, yf], env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
+    ys, o = np.fromfile(yf, dtype=dt).astype(np.complex128), 0
+    out = []
+    for c in pattern:
+        L = m if c == "Q" else n
+        out.append(ys[o:o + L])
+        o += L
+    return out
+
+
+@pytest.mark.parametrize("ens,m,n,pattern", [
+    (1, 1500, 1500, "QQHQQH"), (0, 1300, 900, "QHHQQH"), (0, 700, 700, "QGQG")])
+def test_complex_queries_emulated(driver, tmp_path, ens, m, n, pattern):
+    rng = np.random.default_rng(m + n)
+    xs = [rng.standard_normal(m if c == "H" else n) +
+          1j * rng.standard_normal(m if c == "H" else n) for c in pattern]
+    xs[2] = np.zeros_like(xs[2])
+    sig = 0.5 if ens == 0 else 1.0
+    ys = _crun_queries(driver, tmp_path, ens, m, n, 1, sig, pattern, xs)
+    tq = sum(2 if c == "G" else 1 for c in pattern)
+    orc = oracle.CHDOracle(ens, n, m=m, tmax=tq, seed=3, trial=4, sigma=sig)
+    for c, x, y in zip(pattern, xs, ys):
+        if c == "G":
+            want = (orc.mv(x) + orc.rmv(x)) / np.sqrt(2)
+        else:
+            want = orc.query(x, c == "H")
+        assert np.abs(y - want).max() <= 1e-12 * max(np.abs(want).max(), 1)
+
+
+def test_complex_haar_trajectory_emulated(driver, tmp_path):
+    n, T, a, b = 2100, 12, 1.0, 0.1
+    rng = np.random.default_rng(1)
+    x1 = (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    x1.astype(np.complex64).tofile(str(tmp_path / "x1.bin"))
+    pre = str(tmp_path / "run")
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([driver, "crun", str(n), str(T), str(a), str(b), "0",
+                        "5", "6", str(tmp_path / "x1.bin"), pre], env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "runtime error" not in r.stderr
+    assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
+    X = np.fromfile(pre + ".X", dtype=np.complex64).reshape(T + 1, n)
+    Y = np.fromfile(pre + ".Y", dtype=np.complex64).reshape(T, n)
+    X, Y = X.astype(np.complex128), Y.astype(np.complex128)
+    orc = oracle.CHDOracle(oracle.HAAR, n, tmax=T, seed=5, trial=6)
+    for t in range(T):
+        assert relerr(Y[t], orc.mv(X[t])) < 1e-5
+        assert np.abs(oracle.f_ctanh(Y[t], X[t], a, b) - X[t + 1]).max() < 1e-6

@@ -1,0 +1,181 @@
+"""Complex HD on the GPU (Sec. 3.4; hd_c* / CLazyMatrix): the complex
+Ginibre ensemble, the unitary group U(n) and the GUE composition, against the
+complex FP64 oracle.
+
+* FP64 storage, free run (Mode A): every answer of mixed Q / Q^H sequences
+  within 1e-11 of the oracle (rectangular Ginibre, Haar, GUE), at sizes that
+  span several 1024-row workgroups with a ragged tail;
+* FP32 storage: the oracle answers the GPU's own query vectors (Mode B) of a
+  fused Haar trajectory (map tanh(a|y|) e^{i arg y} + b x) at n = 100003 and
+  of a mixed Ginibre sequence, within 1e-4 (FP32 panels: the reflector phase
+  e^{i theta} = v_1 / |v_1| moves by about eps_32 ||v|| / |v_1|, i.e. by
+  eps_32 sqrt(n) for a generic pivot; 1e-4 leaves a margin of 20 at
+  n = 1e5), and the unitary invariants ||y_t|| = ||x_t|| and
+  Y^H Y = X^H X over the whole trajectory;
+* laws: |Q_11|^2 ~ Beta(1, n - 1) and E Q_11^2 = 0 over many Haar keys;
+* the GUE matrix rebuilt column by column is Hermitian;
+* edge cases: a zero query (identity reflector), capacity, non-finite
+  input and reset.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2101_07464_amd as hd  # noqa: E402
+from paper_2101_07464_amd import _lib  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def crand(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _dev(x, dtype):
+    return torch.from_numpy(np.asarray(x, dtype=np.complex128)).to(DEV, dtype)
+
+
+def _host(y):
+    return y.to(torch.complex128).cpu().numpy()
+
+
+@pytest.mark.parametrize("ens,m,n,pattern", [
+    (hd.HAAR, 3001, 3001, "QQHQHHQQQHQHQQQQHQQH"),
+    (hd.GINIBRE, 2500, 1700, "QHHQQHQQHQHHQHQQ"),
+    (hd.GINIBRE, 1031, 2049, "HQQHQHQQHHQ"),
+])
+def test_fp64_mixed_queries_match_oracle(ens, m, n, pattern):
+    rng = np.random.default_rng(len(pattern) + m)
+    sig = 0.7 if ens == hd.GINIBRE else 1.0
+    A = hd.CLazyMatrix(ens, n, m=m, t_max=len(pattern), seed=11, trial=5,
+                       sigma=sig, dtype=torch.complex128, device=DEV)
+    orc = oracle.CHDOracle(ens, n, m=m, tmax=len(pattern), seed=11, trial=5,
+                           sigma=sig)
+    worst = 0.0
+    for t, c in enumerate(pattern):
+        adj = c == "H"
+        x = crand(rng, m if adj else n)
+        if t == 6:
+            x = np.zeros_like(x)        # identity reflector
+        y = _host(A.query(_dev(x, torch.complex128), adj))
+        want = orc.query(x, adj)
+        if t == 6:
+            assert np.abs(y).max() == 0.0 and np.abs(want).max() == 0.0
+            continue
+        worst = max(worst, relerr(y, want))
+    assert A.status() == 0
+    assert A.counts() == orc.counts()
+    print("FP64 %s %dx%d: worst %.2e" % ("Haar" if ens else "Ginibre", m, n,
+                                         worst))
+    assert worst < 1e-11
+
+
+def test_fp64_gue_matches_oracle_and_is_hermitian():
+    n = 1200
+    rng = np.random.default_rng(3)
+    A = hd.CLazyMatrix(hd.GINIBRE, n, t_max=12, seed=2, trial=9, sigma=1.3,
+                       dtype=torch.complex128, device=DEV)
+    orc = oracle.CHDOracle(oracle.GINIBRE, n, tmax=12, seed=2, trial=9,
+                           sigma=1.3)
+    worst = 0.0
+    for _ in range(6):
+        x = crand(rng, n)
+        y = _host(A.gue_mv(_dev(x, torch.complex128)))
+        worst = max(worst, relerr(y, (orc.mv(x) + orc.rmv(x)) / np.sqrt(2)))
+    assert worst < 1e-11
+    # a full reconstruction at small n
+    k = 40
+    B = hd.CLazyMatrix(hd.GINIBRE, k, t_max=2 * k, seed=4, trial=0,
+                       sigma=1.0, dtype=torch.complex128, device=DEV)
+    G = np.array([_host(B.gue_mv(_dev(e, torch.complex128)))
+                  for e in np.eye(k, dtype=complex)]).T
+    assert np.abs(G - G.conj().T).max() < 1e-12
+    assert np.abs(np.diag(G).imag).max() < 1e-12
+
+
+def test_fp32_haar_trajectory_mode_b_and_invariants():
+    n, T, a, b = 100_003, 60, 1.0, 0.1
+    rng = np.random.default_rng(7)
+    x1 = crand(rng, n) / np.sqrt(2)
+    A = hd.CLazyMatrix(hd.HAAR, n, t_max=T, seed=21, trial=2,
+                       dtype=torch.complex64, device=DEV)
+    X, Y = A.run(_dev(x1, torch.complex64), T, a, b)
+    torch.cuda.synchronize()
+    assert A.status() == 0
+    X, Y = _host(X), _host(Y)
+    # the map, entry by entry, in FP64 on the FP32 answers
+    em = max(np.abs(oracle.f_ctanh(Y[t], X[t], a, b) - X[t + 1]).max()
+             for t in range(T))
+    assert em < 1e-6
+    orc = oracle.CHDOracle(oracle.HAAR, n, tmax=T, seed=21, trial=2)
+    eb = max(relerr(Y[t], orc.mv(X[t])) for t in range(T))
+    iso = max(abs(np.linalg.norm(Y[t]) / np.linalg.norm(X[t]) - 1)
+              for t in range(T))
+    gx, gy = X[:T].conj() @ X[:T].T, Y.conj() @ Y.T
+    gram = np.abs(gy - gx).max() / np.abs(gx).max()
+    print("FP32 Haar n=%d T=%d: Mode B %.2e, isometry %.2e, Gram %.2e"
+          % (n, T, eb, iso, gram))
+    assert eb < 1e-4
+    assert iso < 1e-5 and gram < 1e-5
+
+
+def test_fp32_ginibre_mixed_mode_b():
+    m, n = 40_000, 50_001
+    pattern = "QHQQHHQHQQ" * 3
+    rng = np.random.default_rng(8)
+    A = hd.CLazyMatrix(hd.GINIBRE, n, m=m, t_max=len(pattern), seed=3,
+                       trial=1, sigma=1 / np.sqrt(n), dtype=torch.complex64,
+                       device=DEV)
+    orc = oracle.CHDOracle(oracle.GINIBRE, n, m=m, tmax=len(pattern), seed=3,
+                           trial=1, sigma=1 / np.sqrt(n))
+    worst = 0.0
+    for c in pattern:
+        adj = c == "H"
+        xd = _dev(crand(rng, m if adj else n), torch.complex64)
+        y = _host(A.query(xd, adj))
+        worst = max(worst, relerr(y, orc.query(_host(xd), adj)))
+    print("FP32 Ginibre %dx%d mixed: Mode B %.2e" % (m, n, worst))
+    assert worst < 1e-4
+
+
+def test_haar_unitary_first_column_law():
+    n, N = 64, 3000
+    A = hd.CLazyMatrix(hd.HAAR, n, t_max=1, seed=0, trial=0,
+                       dtype=torch.complex128, device=DEV)
+    e1 = _dev(np.eye(n, dtype=complex)[0], torch.complex128)
+    q = np.empty(N, dtype=complex)
+    for tr in range(N):
+        A.reset(77, tr)
+        q[tr] = _host(A.mv(e1))[0]
+    assert stats.kstest(np.abs(q) ** 2, stats.beta(1, n - 1).cdf).pvalue > 1e-3
+    sq = q * q
+    assert abs(sq.mean()) < 5 * np.sqrt(np.mean(np.abs(sq) ** 2) / N)
+
+
+def test_capacity_nonfinite_and_reset():
+    n = 300
+    A = hd.CLazyMatrix(hd.GINIBRE, n, m=5, t_max=10, seed=1, trial=0,
+                       dtype=torch.complex64, device=DEV)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        A.rmv(_dev(crand(rng, 5), torch.complex64))
+    with pytest.raises(_lib.HDCapacityError):   # l = m reflectors already
+        A.rmv(_dev(crand(rng, 5), torch.complex64))
+    assert A.counts() == (5, 0, 5)
+    x = crand(rng, n)
+    x[3] = np.nan
+    A.mv(_dev(x, torch.complex64))
+    assert A.status() == _lib.HD_ERR_NONFINITE
+    A.reset(1, 0)
+    assert A.status() == 0 and A.counts() == (0, 0, 0)
+    y = _host(A.mv(_dev(np.ones(n), torch.complex64)))
+    orc = oracle.CHDOracle(oracle.GINIBRE, n, m=5, tmax=10, seed=1, trial=0)
+    assert relerr(y, orc.mv(np.ones(n))) < 1e-5
