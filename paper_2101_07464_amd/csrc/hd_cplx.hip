@@ -20,13 +20,15 @@
 // vector; random side G), in launches:
 //   L1  dots: w = U_D^H x (and d = B_D^H x on Ginibre) | random side: the dots
 //       of U_G with the fresh draw g (and, on Haar, g written into the new
-//       column of U_G with its norm and pivot);
-//   S1  z = T_D^H w;
+//       column of U_G with its norm and pivot); the panel whose last column
+//       came from the previous query's data pass also dots its earlier
+//       columns with that column, in the same sweep;
+//   S1  that pending T column, then z = T_D^H w;
 //   L2  data pass: p = Delta_D (x - U_D z); rows below the new reflector's
-//       index k are kept (head), row k is its pivot, rows > k its column;
-//       then the dots of the old columns with the new one (T column);
-//   S2  the new reflectors' scalars and T columns, then the coefficients of
-//       the output;
+//       index k are kept (head), row k is its pivot, rows > k its column
+//       (its T column waits for the next L1, which streams the panel anyway);
+//   S2  the new reflectors' scalars (and, on Haar, the draw side's T column),
+//       then the coefficients of the output;
 //   L3  output pass over the random side: Haar y = (I - U_G T_G U_G^H)
 //       Delta_G^* (p_head, ||p_tail||, 0..); Ginibre (Alg. 1 with ^H)
 //       y = sigma (B_G a + nu u_t + Delta^* b - U_G c_b) and the new explicit
@@ -68,7 +70,7 @@ inline RedLay red_lay(int kmax) {
   r.w = 0;             // U_D^H x
   r.d = 2 * kmax;      // B_D^H x (Ginibre)
   r.e = 4 * kmax;      // random-side dots with the draw
-  r.t = 6 * kmax;      // data pass: old columns with the new one
+  r.t = 6 * kmax;      // pending column: earlier columns with it
   r.s = 8 * kmax;      // [0] ssq of the data tail, [1] ssq of the draw tail
   r.end = 8 * kmax + 8;
   return r;
@@ -90,7 +92,11 @@ inline CoefLay coef_lay(int kmax) {
 }
 
 // Per-reflector FP64 scalars.
-enum { kRefNu = 0, kRefR, kRefCos, kRefSin, kRefTau, kRefIdent, kRefStride = 8 };
+enum {
+  kRefNu = 0, kRefR, kRefCos, kRefSin, kRefTau, kRefIdent,
+  kRefUp = 6,  // pivot entry of u (complex, FP64)
+  kRefStride = 8
+};
 // Scalars.
 enum {
   kScPivD = 0,   // pivot of the data tail (complex)
@@ -168,15 +174,18 @@ __device__ __forceinline__ int64_t row_of(int64_t blk, int e) {
   return blk * kRowsWG + wave * kRowsWave + e * 64 + lane;
 }
 
-// Partial dots over this wave's rows: out[2 j] + i out[2 j + 1] =
-// sum_i conj(P[i, j]) b_i for j < nc (out: this wave's partial row).
-// Every panel row up to ld is allocated and zero beyond the dimension.
-template <typename T>
+// Partial dots over this wave's rows: out0[2 j] + i out0[2 j + 1] =
+// sum_i conj(P[i, j]) b0_i for j < nc and, with NR = 2, likewise b1 into
+// out1 for j < nc1 (out: this wave's partial row), each panel entry loaded
+// once.  Every panel row up to ld is allocated and zero beyond the dimension.
+template <typename T, int NR>
 __device__ __forceinline__ void cdots(const T* __restrict__ P, int64_t ld,
                                       int nc, const int64_t (&row)[kRPT],
-                                      const cd (&b)[kRPT], double* out) {
-  constexpr int CG = sizeof(T) == 4 ? 8 : 4;  // complex columns per group
-  constexpr int NV = 2 * CG;
+                                      const cd (&b0)[kRPT],
+                                      const cd (&b1)[kRPT], int nc1,
+                                      double* out0, double* out1) {
+  constexpr int CG = (sizeof(T) == 4 ? 8 : 4) / NR;  // columns per group
+  constexpr int NV = 2 * CG * NR;
   constexpr int kStep = 64 / NV;
   const int lane = threadIdx.x & 63;
   for (int j0 = 0; j0 < nc; j0 += CG) {
@@ -190,15 +199,24 @@ __device__ __forceinline__ void cdots(const T* __restrict__ P, int64_t ld,
 #pragma unroll
         for (int e = 0; e < kRPT; ++e) {
           const cd u = ldc<T>(col, row[e]);
-          v[2 * c] += u.re * b[e].re + u.im * b[e].im;
-          v[2 * c + 1] += u.re * b[e].im - u.im * b[e].re;
+          v[2 * c] += u.re * b0[e].re + u.im * b0[e].im;
+          v[2 * c + 1] += u.re * b0[e].im - u.im * b0[e].re;
+          if (NR == 2) {
+            v[2 * CG + 2 * c] += u.re * b1[e].re + u.im * b1[e].im;
+            v[2 * CG + 2 * c + 1] += u.re * b1[e].im - u.im * b1[e].re;
+          }
         }
       }
     }
     const double r = wave_reduce_scatter<NV>(v);
     if (lane % kStep == 0) {
       const int q = lane / kStep;
-      if (j0 + q / 2 < nc) out[2 * j0 + q] = r;
+      if (q < 2 * CG) {
+        if (j0 + q / 2 < nc) out0[2 * j0 + q] = r;
+      } else if (NR == 2) {
+        const int q1 = q - 2 * CG;
+        if (j0 + q1 / 2 < nc1) out1[2 * j0 + q1] = r;
+      }
     }
   }
 }
@@ -267,6 +285,8 @@ struct DotsJob {
   int pstride;
   int slot1, slot2;    // partial slots of the P1 and P2 dots
   int ssq_slot;        // >= 0: sum |b_i|^2 over rows >= glo
+  int pk;              // >= 0: P1's column pk (rows > pk) is a second
+  int pslot;           //   right-hand side for its columns < pk (slots pslot)
   int nwg;
 };
 
@@ -302,8 +322,23 @@ __device__ __forceinline__ void dots_job(const DotsJob& j, int64_t blk) {
     b[e] = v;
   }
   double* out = j.part + (blk * kWaves + wave) * (int64_t)j.pstride;
-  if (j.nc1 > 0) cdots<T>((const T*)j.P1, j.ld, j.nc1, row, b, out + j.slot1);
-  if (j.nc2 > 0) cdots<T>((const T*)j.P2, j.ld, j.nc2, row, b, out + j.slot2);
+  if (j.pk >= 0) {
+    // the pending T column of this panel: the dots of its earlier columns
+    // with column pk (rows > pk), in the same sweep as the dots with b
+    const T* pc = (const T*)j.P1 + 2 * (int64_t)j.pk * j.ld;
+    cd b1[kRPT];
+#pragma unroll
+    for (int e = 0; e < kRPT; ++e)
+      b1[e] = row[e] > j.pk ? ldc<T>(pc, row[e]) : cd{0.0, 0.0};
+    cdots<T, 2>((const T*)j.P1, j.ld, j.nc1, row, b, b1, j.pk,
+                out + j.slot1, out + j.pslot);
+  } else if (j.nc1 > 0) {
+    cdots<T, 1>((const T*)j.P1, j.ld, j.nc1, row, b, b, 0, out + j.slot1,
+                nullptr);
+  }
+  if (j.nc2 > 0)
+    cdots<T, 1>((const T*)j.P2, j.ld, j.nc2, row, b, b, 0, out + j.slot2,
+                nullptr);
   if (j.ssq_slot >= 0) {
     const double s = wave_sum(ssq);
     if (lane == 0) out[j.ssq_slot] = s;
@@ -371,7 +406,7 @@ struct CxPassArgs {
   double* piv;
   void* newcol;        // column k of U (rows > k)
   double* part;
-  int pstride, tslot, ssq_slot;
+  int pstride, ssq_slot;
   // output passes
   void* y;
   const void* comb;    // non-null: y = (comb + y) / sqrt(2)
@@ -403,12 +438,10 @@ __global__ __launch_bounds__(kWG) void k_cx_pass(CxPassArgs a) {
   if (MODE == kModeData) {
     cgemv<T>(U, a.ld, a.k, row, a.coef + a.cl.z, acc);
     const int k = a.k;
-    cd u[kRPT];
     double ssq = 0.0;
 #pragma unroll
     for (int e = 0; e < kRPT; ++e) {
       const int64_t i = row[e];
-      cd un{0.0, 0.0};
       if (i < a.dim) {
         cd p = cadd(ldc<T>((const T*)a.x, i), acc[e]);
         if (k > 0) p = cmul(ld2(a.del + 2 * (i < k ? i : k - 1)), p);
@@ -419,15 +452,13 @@ __global__ __launch_bounds__(kWG) void k_cx_pass(CxPassArgs a) {
           st2(a.piv, p);
           ssq += p.re * p.re + p.im * p.im;
         } else {
-          un = roundc<T>(p);
+          const cd un = roundc<T>(p);
           stc<T>((T*)a.newcol, i, un);
           ssq += un.re * un.re + un.im * un.im;
         }
       }
-      u[e] = un;
     }
     double* out = a.part + (blk * kWaves + wave) * (int64_t)a.pstride;
-    if (k > 0) cdots<T>(U, a.ld, k, row, u, out + a.tslot);
     const double s = wave_sum(ssq);
     if (lane == 0) out[a.ssq_slot] = s;
     return;
@@ -500,6 +531,8 @@ struct SmallArgs {
   double* scal;
   int* flag;
   int f64;
+  SideDev P;           // side with a pending T column (pk >= 0)
+  int pk;
 };
 
 __device__ __forceinline__ double* tij(double* T, int kmax, int i, int j) {
@@ -551,6 +584,8 @@ __device__ void build_reflector(const SideDev& S, int f64, int k, double ss,
   rf[kRefNu] = nu;
   rf[kRefCos] = cth;
   rf[kRefSin] = sth;
+  rf[kRefUp] = upiv.re;
+  rf[kRefUp + 1] = upiv.im;
   uset(S, f64, k, k, upiv);
   const cd prev = k > 0 ? ld2(S.del + 2 * (k - 1)) : cd{1.0, 0.0};
   st2(S.del + 2 * k, cmul(prev, c));
@@ -578,6 +613,17 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
   __shared__ cd piv[2];
   const int tid = threadIdx.x, kmax = a.kmax;
   if (PH == 0) {
+    if (a.pk >= 0) {
+      // the pending T column: dots of the earlier columns with the new one,
+      // rows > pk from this query's dots launch, the pivot row here
+      const int pk = a.pk;
+      const cd up = ld2(a.P.ref + (int64_t)pk * kRefStride + kRefUp);
+      for (int j = tid; j < pk; j += kWG)
+        h[j] = cadd(ld2(a.red + a.rl.t + 2 * j), cjmul(uent(a.P, a.f64, pk, j), up));
+      __syncthreads();
+      t_column(a.P, kmax, pk, h);
+      __syncthreads();
+    }
     const int k = a.kD;
     for (int j = tid; j < k; j += kWG) {
       cd z{0.0, 0.0};
@@ -593,7 +639,6 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
     cd up;
     build_reflector(a.D, a.f64, kD, a.red[a.rl.s + 0], ld2(a.scal + kScPivD),
                     up, a.flag);
-    piv[0] = up;
     a.scal[kScNuD] = a.D.ref[(int64_t)kD * kRefStride + kRefNu];
     if (PH == 1) {
       build_reflector(a.G, a.f64, kD, a.red[a.rl.s + 1],
@@ -602,17 +647,16 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
     }
   }
   __syncthreads();
-  // dots of the old columns with the new ones: rows > k from the passes,
+  // the data side's T column waits for the next query's dots launch; the
+  // draw side's (Haar) is complete: rows > k from this query's dots launch,
   // row k (the pivot) here
-  for (int j = tid; j < kD; j += kWG) {
-    h[j] = cadd(ld2(a.red + a.rl.t + 2 * j), cjmul(uent(a.D, a.f64, kD, j), piv[0]));
-    if (PH == 1)
+  if (PH == 1) {
+    for (int j = tid; j < kD; j += kWG)
       h2[j] = cadd(ld2(a.red + a.rl.e + 2 * j), cjmul(uent(a.G, a.f64, kD, j), piv[1]));
+    __syncthreads();
+    t_column(a.G, kmax, kD, h2);
+    __syncthreads();
   }
-  __syncthreads();
-  t_column(a.D, kmax, kD, h);
-  if (PH == 1) t_column(a.G, kmax, kD, h2);
-  __syncthreads();
   if (PH == 1) {
     // s = Delta_G^* (p_0..p_{k-1}, nu_D) over rows <= k, then
     // c = T_G (U_G^H s) over the k + 1 columns
@@ -691,6 +735,7 @@ struct hd_cctx {
   double sigma;
   hipStream_t stream;
   int t, r, l;
+  int pend_side, pend_k;  // the side whose last T column is pending
   SideDev S[2];     // 0: R (C^n), 1: L (C^m)
   void* B[2];       // Ginibre basis panels
   int64_t dim[2];
@@ -792,6 +837,7 @@ DotsJob no_job() {
   DotsJob j;
   std::memset(&j, 0, sizeof(j));
   j.ssq_slot = -1;
+  j.pk = -1;
   return j;
 }
 
@@ -809,7 +855,8 @@ RedJob red_job(const double* part, int64_t nrows, int pstride, double* out) {
 // the new column written.
 double dots_bytes(const hd_cctx* h, const DotsJob& j) {
   if (!j.nwg) return 0.0;
-  double cols = j.nc1 + j.nc2 + (j.x ? 1 : 0) + (j.wcol ? 1 : 0);
+  double cols = j.nc1 + j.nc2 + (j.x ? 1 : 0) + (j.wcol ? 1 : 0) +
+                (j.pk >= 0 ? 1 : 0);
   return cols * (double)j.dim * h->es;
 }
 
@@ -905,6 +952,10 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
     jd.slot1 = h->rl.w;
     jd.slot2 = h->rl.d;
     jd.nwg = h->nwg[D];
+    if (h->pend_side == D) {
+      jd.pk = h->pend_k;
+      jd.pslot = h->rl.t;
+    }
   }
   if (haar || kG > 0) {
     jg.P1 = SG.U;
@@ -924,6 +975,10 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
     jg.pstride = h->pstride;
     jg.slot1 = h->rl.e;
     jg.nwg = h->nwg[G];
+    if (h->pend_side == G) {
+      jg.pk = h->pend_k;
+      jg.pslot = h->rl.t;
+    }
   }
   CXCHK(launch_dots(h, jd, jg));
   RedJob rd = red_job(h->part[D], (int64_t)h->nwg[D] * kWaves, h->pstride,
@@ -935,12 +990,16 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
     rd.count[0] = 2 * kD;
     rd.start[1] = h->rl.d;
     rd.count[1] = haar ? 0 : 2 * kG;
+    rd.start[2] = h->rl.t;
+    rd.count[2] = jd.pk >= 0 ? 2 * jd.pk : 0;
   }
   if (jg.nwg) {
     rg.start[0] = h->rl.e;
     rg.count[0] = 2 * kG;
     rg.start[1] = h->rl.s + 1;
     rg.count[1] = haar ? 1 : 0;
+    rg.start[2] = h->rl.t;
+    rg.count[2] = jg.pk >= 0 ? 2 * jg.pk : 0;
   }
   CXCHK(launch_reduce(h, rd, rg));
 
@@ -959,7 +1018,13 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
   sa.scal = h->scal;
   sa.flag = h->flag;
   sa.f64 = h->f64;
-  if (kD > 0) CXCHK(launch_small<0>(h, sa));
+  sa.pk = -1;
+  if (h->pend_side >= 0) {
+    sa.P = h->S[h->pend_side];
+    sa.pk = h->pend_k;
+  }
+  if (kD > 0 || sa.pk >= 0) CXCHK(launch_small<0>(h, sa));
+  h->pend_side = h->pend_k = -1;
 
   // L2: data pass
   CxPassArgs pa;
@@ -977,15 +1042,12 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
   pa.newcol = (char*)SD.U + (size_t)es2 * SD.ld * kD;
   pa.part = h->part[D];
   pa.pstride = h->pstride;
-  pa.tslot = h->rl.t;
   pa.ssq_slot = h->rl.s + 0;
   CXCHK(launch_pass<kModeData>(h, D, pa));
   RedJob r2 = red_job(h->part[D], (int64_t)h->nwg[D] * kWaves, h->pstride,
                       h->red);
-  r2.start[0] = h->rl.t;
-  r2.count[0] = 2 * kD;
-  r2.start[1] = h->rl.s + 0;
-  r2.count[1] = 1;
+  r2.start[0] = h->rl.s + 0;
+  r2.count[0] = 1;
   CXCHK(launch_reduce(h, r2, red_job(nullptr, 0, 0, nullptr)));
 
   // S2 and L3
@@ -1001,6 +1063,8 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
   po.scal = h->scal;
   if (haar) {
     CXCHK(launch_small<1>(h, sa));
+    h->pend_side = D;
+    h->pend_k = kD;
     po.k = kD;
     po.xmap = xmap;
     po.xnext = xnext;
@@ -1012,6 +1076,8 @@ int cx_query(hd_cctx* h, int adj, const void* x, void* y, const void* comb,
     h->l += 1;
   } else {
     CXCHK(launch_small<2>(h, sa));
+    h->pend_side = D;
+    h->pend_k = kD;
     po.k = kG;
     po.B = h->B[G];
     po.kb = kD;
@@ -1096,6 +1162,7 @@ int hd_cinit(int32_t ensemble, int32_t storage, int64_t m, int64_t n,
   CXA(h->scal, sizeof(double) * kScCount);
   CXA(h->flag, sizeof(int) * 4);
   h->ybuf = nullptr;
+  h->pend_side = h->pend_k = -1;
 #undef CXA
   rc = cx_zero_state(h);
   if (rc != HD_OK) return fail(rc);
@@ -1147,6 +1214,7 @@ int hd_creset(hd_chandle h, uint32_t seed, uint32_t trial) {
   h->seed = seed;
   h->trial = trial;
   h->t = h->r = h->l = 0;
+  h->pend_side = h->pend_k = -1;
   return cx_zero_state(h);
 }
 
