@@ -39,7 +39,16 @@ Workloads (--workload):
       (sd 2), 50 layers with FP32 (a_t, theta_t) = (0.3, 0.6), loss
       ||x_51 - x*||^2; FP32 storage.  A step is --c5-trials trials, each a
       fresh Q: forward pass (101 queries) and reverse pass (98 queries);
-      also timed forward-only.
+      also timed forward-only, and the same trials as one lockstep batch
+      (hd_ista_run + hd_ista_grad) against the trial-by-trial run.
+  goe       50 GOE queries G x_t at n = 65536 (two queries of Q each).
+  spectral  the spectral method of Sec. 2.2: n = 1e5, m = 2e5, 50 power
+            steps of m D through the lazy Haar Q.
+  lasso     the lasso experiment of Sec. 2.1: 1e5 ISTA trials at n = 1000,
+            m = 500, T = 50 in one lockstep batch, beside the direct method
+            (dense Q) on 20000 trials, with both mean squared error curves.
+  cplx      complex HD (Sec. 3.4): U(1e7), T = 200, complex64, map
+            tanh(|y|) e^{i arg y} + 0.1 x.
 """
 import argparse
 import json
@@ -453,6 +462,44 @@ def run_adjoint(args, steps, warmup, K):
     t_f = timed(False)
     if A.status() != 0:
         raise RuntimeError("device reported a non-finite reflector norm")
+    # the same K trials (same keys and inputs) as one lockstep batch
+    # (hd_ista_run + hd_ista_grad)
+    xs_b, nz_b = torch.stack(xs), torch.stack(nz)
+    Bt = hd.IstaBatch(m, n, L, K, seed=0, trial0=0, sigma=sig, device=dev,
+                      grad=True)
+
+    def batch_step(backward):
+        X = Bt.run(a, th, xs_b, nz_b)
+        if backward:
+            return X, Bt.grad(a, th, 2.0 * (X[:, -1] - xs_b))
+        return X, None
+
+    def timed_batch(backward):
+        for _ in range(max(warmup, 1)):
+            batch_step(backward)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch_step(backward)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tb_fb = timed_batch(True)
+    tb_f = timed_batch(False)
+    if Bt.status() != 0:
+        raise RuntimeError("device reported a non-finite reflector norm")
+    # batched against per-trial gradients on sampled trials
+    Xb, (gab, gtb, _) = batch_step(True)
+    gerr = 0.0
+    for b in sorted({0, K // 2, K - 1}):
+        A.reset(0, b)
+        y = A.mv(xs[b]) + nz[b]
+        X1, U1, V1 = A.lista_forward(a, th, z, y)
+        ga1, gt1, _ = A.lista_backward(a, th, U1, V1, 2.0 * (X1[-1] - xs[b]))
+        for p_, q_ in ((gab[b], ga1), (gtb[b], gt1)):
+            gerr = max(gerr, float((p_ - q_).abs().max() /
+                                   q_.abs().max().clamp_min(1e-300)))
+    del Xb, Bt
     W_fb = K * nominal_work(n, tq)
     W_f = K * nominal_work(n, 1 + 2 * L)
     out = {
@@ -468,6 +515,14 @@ def run_adjoint(args, steps, warmup, K):
                          "ms_per_step": t_f * 1e3,
                          "queries_per_trial": 1 + 2 * L},
         "adjoint_time_over_forward": t_fb / t_f,
+        "batched": {"what": "the same trials in one lockstep batch "
+                            "(hd_ista_run + hd_ista_grad)",
+                    "ms_per_step": tb_fb * 1e3,
+                    "forward_only_ms_per_step": tb_f * 1e3,
+                    "value": W_fb / tb_fb, "unit": "elem-updates/s",
+                    "batched_over_serial": t_fb / tb_fb,
+                    "grad_max_rel_err_vs_serial": gerr,
+                    "grad_trials_compared": sorted({0, K // 2, K - 1})},
     }
     return out
 
@@ -963,7 +1018,7 @@ def extras(args, out):
             "workload": a["config"]["workload"], "value": a["value"],
             "unit": a["unit"], "ms_per_step": a["ms_per_step"],
             "trials_per_step": a["config"]["trials_per_step"],
-            "forward_only": a["forward_only"]}
+            "forward_only": a["forward_only"], "batched": a["batched"]}
     except Exception as e:
         out["adjoint_error"] = repr(e)
     out["extras_wall_s"] = time.perf_counter() - t0
@@ -989,7 +1044,7 @@ def main():
                     help="c4 only: skip the batched and differentiated "
                          "ratios")
     ap.add_argument("--extra-steps", type=int, default=2)
-    ap.add_argument("--extra-c5-trials", type=int, default=64)
+    ap.add_argument("--extra-c5-trials", type=int, default=256)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in launch-shape rule instead of "
                          "timing the candidate shapes first")

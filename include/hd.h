@@ -377,17 +377,24 @@ int hd_batch_free(hd_batch b);
  * (two queries each, Algorithm 1).  All trials advance in lockstep, one
  * query index at a time, so a query costs a handful of launches for the
  * whole batch; each trial's answers are those of a separate handle with the
- * same key up to the order of the FP64 partial sums.
+ * same key up to the order of the FP64 partial sums.  With HD_ISTA_GRAD the
+ * batch also runs the reverse pass of the unrolled map (the fixed-Q
+ * gradient of hd_lista_backward, for every trial together).
  * ------------------------------------------------------------------------ */
 typedef struct hd_ista_ctx* hd_ista;
 
+#define HD_ISTA_GRAD 1 /* keep u_t, v_t and room for the reverse pass */
+
 /* Allocate the device state of `count` trials (one arena: per trial four
- * panels of L + 1 or L columns, FP64 scalars, work vectors) on `stream`.
- * Requires L + 1 <= n and L <= m (Algorithm 1's capacity), sigma > 0.
- * Errors: HD_ERR_INVALID, HD_ERR_NOMEM (also beyond 250 GB), HD_ERR_HIP. */
+ * panels, FP64 scalars, work vectors) on `stream`.  flags: 0 or
+ * HD_ISTA_GRAD (then also count x L x n arrays for u_t and v_t, and panel
+ * room for the 2(L - 1) queries of the reverse pass).  Requires L + 1 <= n
+ * and L <= m (Algorithm 1's capacity), with HD_ISTA_GRAD 2L <= n and
+ * 2L - 1 <= m; sigma > 0.  Errors: HD_ERR_INVALID, HD_ERR_NOMEM (also
+ * beyond 250 GB), HD_ERR_HIP. */
 int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
                  int32_t count, uint32_t seed, uint32_t trial0, double sigma,
-                 void* stream, hd_ista* out);
+                 int32_t flags, void* stream, hd_ista* out);
 
 /* Run every trial from fresh matrices (the same keys at every call).
  * a, theta: host arrays of L floats.  xstar: device count x n (x* of trial
@@ -396,6 +403,19 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
  * x_2..x_{L+1}.  Stream-ordered.  Errors: HD_ERR_INVALID, HD_ERR_HIP. */
 int hd_ista_run(hd_ista b, const float* a, const float* theta,
                 const void* xstar, const void* noise, void* X);
+
+/* Reverse pass after hd_ista_run on a batch made with HD_ISTA_GRAD, with the
+ * same a and theta: G (device count x n) holds dL/dx_{L+1} of every trial on
+ * entry and is overwritten (it carries dL/dx_t from layer to layer); grad_a
+ * and grad_theta (device count x L, FP64) receive, for trial i,
+ * dL/da_t = sum(gbar_t u_t) and dL/dtheta_t = -sum(g_{t+1} sign(v_t) m_t)
+ * with the mask m_t = [|v_t| > theta_t], gbar_t = g_{t+1} m_t and
+ * g_t = gbar_t - a_t Q'Q gbar_t (two more queries on the trial's Q per
+ * layer, as hd_lista_backward).  One reverse pass per forward run.
+ * Stream-ordered.  Errors: HD_ERR_INVALID (no HD_ISTA_GRAD, no forward run
+ * since the last reverse pass, null pointers), HD_ERR_HIP. */
+int hd_ista_grad(hd_ista b, const float* a, const float* theta, void* G,
+                 double* grad_a, double* grad_theta);
 
 /* Synchronise and report the sticky device flag (as hd_status). */
 int hd_ista_status(hd_ista b);

@@ -359,10 +359,11 @@ class IstaBatch:
     (``hd_ista_*``): trial i has an m x n Q with N(0, sigma^2) entries keyed
     (seed, trial0 + i), observes y = Q x* + w and runs L layers
     x_{t+1} = soft(x_t + a_t Q'(y - Q x_t), theta_t) from x_1 (zeros by
-    default), all trials in lockstep."""
+    default), all trials in lockstep.  With grad=True, ``grad`` runs the
+    reverse pass of the last ``run`` for every trial."""
 
     def __init__(self, m, n, L, count, seed=0, trial0=0, sigma=1.0,
-                 dtype=None, device="cuda:0"):
+                 dtype=None, device="cuda:0", grad=False):
         torch = _torch()
         dtype = torch.float32 if dtype is None else dtype
         self.m, self.n, self.L, self.count = m, n, L, count
@@ -372,7 +373,8 @@ class IstaBatch:
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().hd_ista_init(
                 _storage(dtype), m, n, L, count, seed, trial0, sigma,
-                _stream_ptr(self.device), ctypes.byref(h)), "hd_ista_init")
+                _lib.HD_ISTA_GRAD if grad else 0, _stream_ptr(self.device),
+                ctypes.byref(h)), "hd_ista_init")
         self._h = h
 
     def __del__(self):
@@ -411,8 +413,71 @@ class IstaBatch:
         self._keep = (xstar, noise)
         return X
 
+    def grad(self, a, theta, g):
+        """Reverse pass of the last run (same a, theta): g = dL/dx_{L+1},
+        (count, n).  Returns (dL/da, dL/dtheta) as (count, L) FP64 tensors
+        (per trial) and dL/dx_2 per trial, (count, n)."""
+        torch = _torch()
+        L = self.L
+        G = g.to(self.device, self.dtype).contiguous().clone()
+        if G.shape != (self.count, self.n):
+            raise ValueError("g must be (count, n)")
+        ga = torch.empty((self.count, L), dtype=torch.float64,
+                         device=self.device)
+        gt = torch.empty_like(ga)
+        af = (ctypes.c_float * L)(*[float(v) for v in a])
+        tf = (ctypes.c_float * L)(*[float(v) for v in theta])
+        Lb = _lib.load()
+        _lib.check(Lb.hd_ista_set_stream(self._h, _stream_ptr(self.device)),
+                   "hd_ista_set_stream")
+        _lib.check(Lb.hd_ista_grad(self._h, af, tf,
+                                   ctypes.c_void_p(G.data_ptr()),
+                                   ctypes.c_void_p(ga.data_ptr()),
+                                   ctypes.c_void_p(gt.data_ptr())),
+                   "hd_ista_grad")
+        return ga, gt, G
+
     def status(self):
         return _lib.load().hd_ista_status(self._h)
+
+
+def _ista_batch_function():
+    torch = _torch()
+
+    class ISTABatch(torch.autograd.Function):
+        """x_{L+1} of every trial of an IstaBatch (made with grad=True),
+        differentiable in the shared per-layer a and theta (1-D tensors of
+        length L): the gradient sums the trials' fixed-Q gradients."""
+
+        @staticmethod
+        def forward(ctx, a, theta, B, xstar, noise):
+            ah = a.detach().float().cpu().tolist()
+            th = theta.detach().float().cpu().tolist()
+            X = B.run(ah, th, xstar, noise)
+            ctx.B, ctx.ah, ctx.th = B, ah, th
+            ctx.like = (a, theta)
+            return X[:, -1].clone()
+
+        @staticmethod
+        def backward(ctx, gx):
+            ga, gt, _ = ctx.B.grad(ctx.ah, ctx.th, gx)
+            a, theta = ctx.like
+            return (ga.sum(0).to(a.device, a.dtype),
+                    gt.sum(0).to(theta.device, theta.dtype), None, None, None)
+
+    return ISTABatch
+
+
+_ISTA_BATCH = None
+
+
+def ista_batch(a, theta, B, xstar, noise):
+    """x_{L+1} of every trial of ``B`` (an IstaBatch with grad=True) as a
+    differentiable function of the shared layer parameters a, theta."""
+    global _ISTA_BATCH
+    if _ISTA_BATCH is None:
+        _ISTA_BATCH = _ista_batch_function()
+    return _ISTA_BATCH.apply(a, theta, B, xstar, noise)
 
 
 def _lista_function():

@@ -19,6 +19,7 @@ HD_ERR_NONFINITE = -5
 HD_ERR_UNSUPPORTED = -6
 HD_ERR_TOO_LARGE = -7
 HD_NOALLOC_SCRATCH_BYTES = 64 << 20
+HD_ISTA_GRAD = 1
 
 HD_GINIBRE = 0
 HD_HAAR = 1
@@ -40,8 +41,8 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
            "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
            "hd_noalloc_scratch_bytes", "hd_spectral_power", "hd_ista_init",
-           "hd_ista_run", "hd_ista_status", "hd_ista_set_stream",
-           "hd_ista_free", "hd_cinit", "hd_cstep", "hd_crun",
+           "hd_ista_run", "hd_ista_grad", "hd_ista_status",
+           "hd_ista_set_stream", "hd_ista_free", "hd_cinit", "hd_cstep", "hd_crun",
            "hd_cgue_step", "hd_creset", "hd_ccounts", "hd_cstatus",
            "hd_cset_stream", "hd_cfree", "hd_cprofile", "hd_cprofile_read"]
 
@@ -127,7 +128,9 @@ def load():
                                            P(ctypes.c_size_t)]),
         "hd_spectral_power": (i32, [vp, i64, vp, vp, i32, dbl, vp, vp]),
         "hd_ista_init": (i32, [i32, i64, i64, i32, i32, ctypes.c_uint32,
-                               ctypes.c_uint32, dbl, vp, P(vp)]),
+                               ctypes.c_uint32, dbl, i32, vp, P(vp)]),
+        "hd_ista_grad": (i32, [vp, P(ctypes.c_float), P(ctypes.c_float), vp,
+                               vp, vp]),
         "hd_ista_run": (i32, [vp, P(ctypes.c_float), P(ctypes.c_float), vp,
                               vp, vp]),
         "hd_ista_status": (i32, [vp]),

@@ -324,10 +324,11 @@ struct IstaSide {
 struct IstaTrialDev {
   IstaSide s[2];
   void* yobs;  // m: the observation y = sigma Q x* + w
-  void* res;   // m: y - Q x_t
+  void* res;   // m: y - Q x_t (reverse pass: Q gbar)
   void* U;     // n: Q'(y - Q x_t) (query output)
   void* V;     // n: x_t + a_t Q'(y - Q x_t)
   void* Yq;    // m: Q x_t (query output)
+  void* gbar;  // n: reverse pass, g masked by the threshold (or null)
 };
 
 struct IstaStep {
@@ -342,6 +343,28 @@ struct IstaStep {
   const void* xstar;
   const void* noise;
   void* X;
+  // kept for the reverse pass (or null): u_t and v_t of every layer,
+  // trial i's layer t at offset (i * L + t) * n
+  void* Urec;
+  void* Vrec;
+  // reverse pass: 1 for its queries (Q gbar, then Q'(.) with
+  // g <- gbar - a_t Q'Q gbar written into G, trial i at offset i * n)
+  int bwd;
+  void* G;
+};
+
+// The reverse pass's per-layer reductions for every trial of a batch.
+struct IstaAdjArgs {
+  const IstaTrialDev* D;
+  const void* G;      // dL/dx_{t+1}, count x n
+  const void* Urec;
+  const void* Vrec;
+  int t, L, nwg;      // layer (0-based), layers, workgroups per trial
+  int64_t n;
+  double theta;
+  double* part;       // count x nwg x 2
+  double* grad_a;     // count x L (FP64)
+  double* grad_theta;
 };
 
 // Phases of one query for all trials; each returns 0 or a HIP error.
@@ -353,6 +376,8 @@ int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
                      IstaStep st, hipStream_t s);
 int launch_ista_rand(int f64, int side, int nblk, const IstaTrialDev* d,
                      IstaStep st, hipStream_t s);
+int launch_ista_adj(int f64, int ntrials, const IstaAdjArgs& a,
+                    hipStream_t s);
 
 // Device-to-device copies of 4-byte words, one workgroup per job.// Device-to-device copies of 4-byte words, one workgroup per job.
 struct CopyJob {

@@ -1,8 +1,10 @@
 // hd_ista.hip -- C-ABI runtime of batches of unrolled-ISTA trials on
 // Gaussian matrices of one shape m x n (Sec. 2.1, eq. (ista), on Algorithm 1),
-// run in lockstep.  All arithmetic runs in the kernels of hd_kernels.hip;
-// this file lays out every trial's state in one device arena and orders the
-// launches of each query index.
+// run in lockstep, and of their reverse pass (the gradient with respect to
+// the per-layer step and threshold, on the same lazy matrices).  All
+// arithmetic runs in the kernels of hd_kernels.hip; this file lays out every
+// trial's state in one device arena and orders the launches of each query
+// index.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,6 +24,13 @@ struct hd_ista_ctx {
   hipStream_t stream;
   int count;
   int L;
+  int grad;        // room and buffers for the reverse pass
+  int ran;         // a forward run has ended and no reverse pass followed
+  int kR, kL;      // reflector counts after the last query
+  void* Urec = nullptr;
+  void* Vrec = nullptr;
+  double* adj_part = nullptr;
+  int nwg_adj;     // 256-row workgroups over n (reverse-pass reductions)
   int64_t dim[2];  // n (side R), m (side L)
   int nwg[2];      // workgroups of 256 rows per side
   IstaTrialDev* dev = nullptr;
@@ -78,12 +87,22 @@ int ialloc(hd_ista_ctx* b, P** out, size_t bytes) {
 // Offsets of one trial's buffers inside its block of the arena.
 struct Lay {
   size_t V[2], B[2], T[2], tau[2], nu[2], piv[2], sgn[2], pi[2], red[2];
-  size_t part, w, zD, zG, z2, head, scal, gscal, yobs, res, U, V2, Yq;
+  size_t part, w, zD, zG, z2, head, scal, gscal, yobs, res, U, V2, Yq, gbar;
   size_t end;
 };
 
-Lay layout(const int64_t* ld, int L, int es, int pstride, int maxwg,
-           int64_t n, int64_t m) {
+// Panel columns per side: side R gets a reflector per Q-query and keeps the
+// basis vectors v of the Q'-queries, side L the reverse.  The forward pass
+// is L + 1 Q-queries and L Q'-queries; the reverse pass adds L - 1 of each.
+void capacities(int L, int grad, int cv[2], int cb[2]) {
+  cv[0] = grad ? 2 * L : L + 1;
+  cv[1] = grad ? 2 * L - 1 : L;
+  cb[0] = cv[1];
+  cb[1] = cv[0];
+}
+
+Lay layout(const int64_t* ld, int L, int grad, int es, int pstride,
+           int maxwg, int64_t n, int64_t m) {
   Lay y;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -91,10 +110,9 @@ Lay layout(const int64_t* ld, int L, int es, int pstride, int maxwg,
     o = up256(o + bytes);
     return at;
   };
-  const int tm = L + 1;
-  // side R gets a reflector per Q-query (L + 1 of them) and keeps the v's
-  // of the L Q'-queries; side L the reverse
-  const int cv[2] = {L + 1, L}, cb[2] = {L, L + 1};
+  int cv[2], cb[2];
+  capacities(L, grad, cv, cb);
+  const int tm = cv[0];
   for (int s = 0; s < 2; ++s) {
     y.V[s] = take((size_t)es * ld[s] * cv[s]);
     y.B[s] = take((size_t)es * ld[s] * cb[s]);
@@ -119,8 +137,29 @@ Lay layout(const int64_t* ld, int L, int es, int pstride, int maxwg,
   y.Yq = take((size_t)es * m);
   y.U = take((size_t)es * n);
   y.V2 = take((size_t)es * n);
+  y.gbar = grad ? take((size_t)es * n) : 0;
   y.end = o;
   return y;
+}
+
+// One query index for every trial: data side R (Q-queries) or L.
+int ista_query(hd_ista_ctx* b, IstaStep& st, int ds) {
+  const int gs = 1 - ds, C = b->count, f64 = b->f64;
+  st.kR = b->kR;
+  st.kL = b->kL;
+  st.step = (uint32_t)(st.q + 1);
+  if (b->kR + b->kL > 0) {
+    ILCHK(launch_ista_tdot(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
+    ILCHK(launch_ista_small(f64, 0, ds, C, b->dev, st, b->stream));
+  }
+  ILCHK(launch_ista_data(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
+  ILCHK(launch_ista_small(f64, 1, ds, C, b->dev, st, b->stream));
+  ILCHK(launch_ista_rand(f64, gs, C * b->nwg[gs], b->dev, st, b->stream));
+  if (ds == 0)
+    ++b->kR;
+  else
+    ++b->kL;
+  return HD_OK;
 }
 
 }  // namespace
@@ -129,14 +168,18 @@ extern "C" {
 
 int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
                  int32_t count, uint32_t seed, uint32_t trial0, double sigma,
-                 void* stream, hd_ista* out) {
+                 int32_t flags, void* stream, hd_ista* out) {
   if (!out) return HD_ERR_INVALID;
   *out = nullptr;
   if (storage != HD_F32 && storage != HD_F64) return HD_ERR_INVALID;
   if (m < 1 || n < 1 || L < 1 || count < 1) return HD_ERR_INVALID;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return HD_ERR_INVALID;
-  // Algorithm 1 needs r <= n (L + 1 Q-queries) and l <= m (L Q'-queries)
-  if ((int64_t)L + 1 > n || (int64_t)L > m) return HD_ERR_INVALID;
+  if (flags & ~HD_ISTA_GRAD) return HD_ERR_INVALID;
+  const int grad = (flags & HD_ISTA_GRAD) != 0;
+  // Algorithm 1 needs r <= n (reflectors from Q-queries) and l <= m
+  int cv[2], cb[2];
+  capacities(L, grad, cv, cb);
+  if ((int64_t)cv[0] > n || (int64_t)cv[1] > m) return HD_ERR_INVALID;
   if (n > ((int64_t)1 << 31) || m > ((int64_t)1 << 31)) return HD_ERR_INVALID;
   hd_ista_ctx* b = new (std::nothrow) hd_ista_ctx();
   if (!b) return HD_ERR_NOMEM;
@@ -145,6 +188,10 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
   b->stream = (hipStream_t)stream;
   b->count = count;
   b->L = L;
+  b->grad = grad;
+  b->ran = 0;
+  b->kR = b->kL = 0;
+  b->nwg_adj = (int)((n + 255) / 256);
   b->dim[0] = n;
   b->dim[1] = m;
   int64_t ld[2];
@@ -152,13 +199,14 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
     ld[s] = (b->dim[s] + 255) / 256 * 256;
     b->nwg[s] = (int)(ld[s] / 256);
   }
-  const int tm = L + 1, Q = 2 * L + 1;
+  const int tm = cv[0], Q = grad ? 4 * L - 1 : 2 * L + 1;
   const int slot2 = Q + 1, extra = slot2 + tm + 1;
   const int pstride = extra + kNumExtra;
   const int maxwg = b->nwg[0] > b->nwg[1] ? b->nwg[0] : b->nwg[1];
-  const Lay lay = layout(ld, L, b->es, pstride, maxwg, n, m);
+  const Lay lay = layout(ld, L, grad, b->es, pstride, maxwg, n, m);
   const size_t per = lay.end;
-  if ((double)per * count > 2.5e11) {
+  const double rec = grad ? 2.0 * b->es * (double)L * n * count : 0.0;
+  if ((double)per * count + rec > 2.5e11) {
     delete b;
     return HD_ERR_NOMEM;
   }
@@ -177,6 +225,12 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
   IALLOC(b->jobs, sizeof(CopyJob) * 3 * (size_t)count);
   IALLOC(b->consts, sizeof(double) * 4);
   IALLOC(b->flag, sizeof(int) * 4);
+  if (grad) {
+    const size_t rb = (size_t)b->es * L * (size_t)n * count;
+    IALLOC(b->Urec, rb);
+    IALLOC(b->Vrec, rb);
+    IALLOC(b->adj_part, sizeof(double) * 2 * (size_t)b->nwg_adj * count);
+  }
 #undef IALLOC
   auto fail = [&](int r) {
     release(b);
@@ -276,6 +330,7 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
     d.Yq = A + lay.Yq;
     d.U = A + lay.U;
     d.V = A + lay.V2;
+    d.gbar = grad ? A + lay.gbar : nullptr;
     host[i] = d;
     jobs[3 * (size_t)i] = CopyJob{b->consts, P[0].pi, 2};
     jobs[3 * (size_t)i + 1] = CopyJob{b->consts, P[1].pi, 2};
@@ -301,7 +356,7 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
 int hd_ista_run(hd_ista b, const float* a, const float* theta,
                 const void* xstar, const void* noise, void* X) {
   if (!b || !a || !theta || !xstar || !noise || !X) return HD_ERR_INVALID;
-  const int L = b->L, C = b->count, f64 = b->f64;
+  const int L = b->L;
   // every run starts from fresh matrices: the reflector counts restart
   // and every array a query reads is rewritten before it is read
   IstaStep st;
@@ -310,30 +365,67 @@ int hd_ista_run(hd_ista b, const float* a, const float* theta,
   st.xstar = xstar;
   st.noise = noise;
   st.X = X;
-  int kR = 0, kL = 0;
+  st.Urec = b->Urec;
+  st.Vrec = b->Vrec;
+  b->kR = b->kL = 0;
+  b->ran = 0;
   for (int q = 0; q <= 2 * L; ++q) {
     const int ds = (q == 0 || q % 2 == 1) ? 0 : 1;
-    const int gs = 1 - ds;
     st.q = q;
-    st.kR = kR;
-    st.kL = kL;
-    st.step = (uint32_t)(q + 1);
-    st.last = q == 2 * L;
+    // with a reverse pass to come, the last forward query still prepares
+    // the next one (its data side is the next query's random side)
+    st.last = q == 2 * L && !b->grad;
     if (ds == 1) {
       st.a = a[q / 2 - 1];
       st.theta = theta[q / 2 - 1];
     }
-    if (kR + kL > 0) {
-      ILCHK(launch_ista_tdot(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
-      ILCHK(launch_ista_small(f64, 0, ds, C, b->dev, st, b->stream));
-    }
-    ILCHK(launch_ista_data(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
-    ILCHK(launch_ista_small(f64, 1, ds, C, b->dev, st, b->stream));
-    ILCHK(launch_ista_rand(f64, gs, C * b->nwg[gs], b->dev, st, b->stream));
-    if (ds == 0)
-      ++kR;
-    else
-      ++kL;
+    const int rc = ista_query(b, st, ds);
+    if (rc) return rc;
+  }
+  b->ran = 1;
+  return HD_OK;
+}
+
+int hd_ista_grad(hd_ista b, const float* a, const float* theta, void* G,
+                 double* grad_a, double* grad_theta) {
+  if (!b || !a || !theta || !G || !grad_a || !grad_theta)
+    return HD_ERR_INVALID;
+  if (!b->grad || !b->ran) return HD_ERR_INVALID;
+  const int L = b->L, C = b->count;
+  IstaStep st;
+  std::memset(&st, 0, sizeof(st));
+  st.L = L;
+  st.bwd = 1;
+  st.G = G;
+  IstaAdjArgs ad;
+  std::memset(&ad, 0, sizeof(ad));
+  ad.D = b->dev;
+  ad.G = G;
+  ad.Urec = b->Urec;
+  ad.Vrec = b->Vrec;
+  ad.L = L;
+  ad.nwg = b->nwg_adj;
+  ad.n = b->dim[0];
+  ad.part = b->adj_part;
+  ad.grad_a = grad_a;
+  ad.grad_theta = grad_theta;
+  int q = 2 * L + 1;
+  b->ran = 0;  // the reverse pass uses up the room it was given
+  for (int t = L - 1; t >= 0; --t) {
+    ad.t = t;
+    ad.theta = theta[t];
+    ILCHK(launch_ista_adj(b->f64, C, ad, b->stream));
+    if (t == 0) break;
+    // g <- gbar - a_t Q'Q gbar: two more queries on every trial's Q
+    st.a = a[t];
+    st.q = q++;
+    st.last = 0;
+    int rc = ista_query(b, st, 0);
+    if (rc) return rc;
+    st.q = q++;
+    st.last = t == 1;
+    rc = ista_query(b, st, 1);
+    if (rc) return rc;
   }
   return HD_OK;
 }

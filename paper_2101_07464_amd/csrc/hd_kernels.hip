@@ -1176,6 +1176,7 @@ __device__ __forceinline__ const void* ista_input(const IstaTrialDev& d,
                                                   const IstaStep& st) {
   const int64_t n = d.s[0].td.n;
   if (ds == 1) return d.res;
+  if (st.bwd) return d.gbar;
   if (st.q == 0) return (const T*)st.xstar + (int64_t)trial * n;
   // query 2t - 1 reads x_t, row t - 1 of X
   return ista_row<T>(st, n, trial, (st.q - 1) / 2);
@@ -1233,6 +1234,19 @@ __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
     a.dyn.b = 1.0;
     a.dyn.x = (const T*)st.noise + (int64_t)trial * d.s[1].td.n;
     a.dyn.xnext = d.yobs;
+  } else if (st.bwd && gs == 1) {
+    // reverse pass: q = Q gbar
+    a.y = d.res;
+    a.dyn.kind = 0;
+  } else if (st.bwd) {
+    // reverse pass: g <- gbar - a_t Q' q, in place in G
+    const int64_t n = d.s[0].td.n;
+    a.y = d.U;
+    a.dyn.kind = kDynAxpy;
+    a.dyn.a = st.a;
+    a.dyn.b = 1.0;
+    a.dyn.x = d.gbar;
+    a.dyn.xnext = (T*)st.G + (int64_t)trial * n;
   } else if (gs == 1) {
     // Q x_t, then y - Q x_t
     a.y = d.Yq;
@@ -1244,12 +1258,18 @@ __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
     const int64_t n = d.s[0].td.n;
     const int t = st.q / 2;  // 1-based layer
     a.y = d.U;
+    a.dyn.aux = d.V;
+    if (st.Urec) {
+      // kept for the reverse pass
+      const int64_t row = ((int64_t)trial * st.L + (t - 1)) * n;
+      a.y = (T*)st.Urec + row;
+      a.dyn.aux = (T*)st.Vrec + row;
+    }
     a.dyn.kind = kDynLista;
     a.dyn.a = st.a;
     a.dyn.b = st.theta;
     a.dyn.x = ista_row<T>(st, n, trial, t - 1);
     a.dyn.xnext = ista_row<T>(st, n, trial, t);
-    a.dyn.aux = d.V;
   }
   gin_pass_body<T, 1>(a, blockIdx.x % nwg);
 }
@@ -1289,6 +1309,52 @@ __global__ __launch_bounds__(kWG) void k_ista_small(const IstaTrialDev* D,
     a.h = a.h + kD;
     a.cslot = kD > 0 ? S.pd.cslot : -1;
     gin_small_body<T>(a);
+  }
+}
+
+// The reverse pass of layer t for every trial (one workgroup per 256 rows of
+// a trial): gbar = g [|v_t| > theta_t], and the workgroup's sums of
+// gbar u_t and -g sign(v_t) [|v_t| > theta_t] (dL/da_t, dL/dtheta_t).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_ista_adj(IstaAdjArgs a) {
+  __shared__ double scr[kWaves];
+  const int trial = blockIdx.x / a.nwg, wg = blockIdx.x % a.nwg;
+  const int64_t i = (int64_t)wg * kWG + threadIdx.x;
+  const int64_t row = ((int64_t)trial * a.L + a.t) * a.n;
+  double sa = 0.0, st = 0.0;
+  if (i < a.n) {
+    const double vi = (double)((const T*)a.Vrec)[row + i];
+    const double gi = (double)((const T*)a.G)[(int64_t)trial * a.n + i];
+    const bool on = fabs(vi) > a.theta;
+    const double gb = on ? gi : 0.0;
+    ((T*)a.D[trial].gbar)[i] = (T)gb;
+    sa = gb * (double)((const T*)a.Urec)[row + i];
+    if (on) st = vi > 0.0 ? -gi : gi;
+  }
+  sa = block_sum(sa, scr);
+  st = block_sum(st, scr);
+  if (threadIdx.x == 0) {
+    double* p = a.part + 2 * ((int64_t)trial * a.nwg + wg);
+    p[0] = sa;
+    p[1] = st;
+  }
+}
+
+// Fixed-order sums of a trial's workgroup pairs into its gradients.
+__global__ __launch_bounds__(kWG) void k_ista_adjsum(IstaAdjArgs a) {
+  __shared__ double scr[kWaves];
+  const int trial = blockIdx.x;
+  const double* p = a.part + 2 * (int64_t)trial * a.nwg;
+  double sa = 0.0, st = 0.0;
+  for (int b = threadIdx.x; b < a.nwg; b += kWG) {
+    sa += p[2 * b];
+    st += p[2 * b + 1];
+  }
+  sa = block_sum(sa, scr);
+  st = block_sum(st, scr);
+  if (threadIdx.x == 0) {
+    a.grad_a[(int64_t)trial * a.L + a.t] = sa;
+    a.grad_theta[(int64_t)trial * a.L + a.t] = st;
   }
 }
 
@@ -1621,6 +1687,21 @@ int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<float>), dim3(nblk),
                        dim3(kWG), 0, s, d, side, st);
+  HD_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_ista_adj(int f64, int ntrials, const IstaAdjArgs& a,
+                    hipStream_t s) {
+  const int nblk = ntrials * a.nwg;
+  if (f64)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_adj<double>), dim3(nblk),
+                       dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_adj<float>), dim3(nblk),
+                       dim3(kWG), 0, s, a);
+  HD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_ista_adjsum, dim3(ntrials), dim3(kWG), 0, s, a);
   HD_CHECK_LAUNCH();
   return 0;
 }

@@ -8,8 +8,11 @@
 //   X1_FILE holds N values of the storage type.  Writes OUT_PREFIX.X
 //   ((T+1) x N) and OUT_PREFIX.Y (T x N) and prints "rc <code> status <code>".
 // usage: driver ista M N L COUNT SEED TRIAL0 SIGMA A THETA XSTAR NOISE OUT
+//          [G_FILE GRAD_OUT]
 //   an FP32 batch of unrolled-ISTA trials with constant (A, THETA); XSTAR
 //   (COUNT x N) and NOISE (COUNT x M) files; writes OUT (COUNT x (L+1) x N).
+//   With G_FILE (COUNT x N, dL/dx_{L+1}) the batch also runs its reverse
+//   pass and writes GRAD_OUT: dL/da (COUNT x L), dL/dtheta (COUNT x L), FP64.
 // usage: driver cplx ENS M N F64 SEED TRIAL SIGMA PATTERN X_FILE OUT
 //   complex queries on one handle: PATTERN is a string of Q (y = Q x),
 //   H (y = Q^H x) and G (GUE step); X_FILE holds the query vectors back to
@@ -56,9 +59,20 @@ static int ista_main(char** argv) {
   void* w = read_file(argv[12], 4 * (size_t)C * m);
   const size_t xb = 4 * (size_t)C * (L + 1) * n;
   void* X = std::calloc(1, xb);
+  const bool grad = argv[14] != nullptr;
   hd_ista b = nullptr;
-  int rc = hd_ista_init(HD_F32, m, n, L, C, seed, trial0, sigma, nullptr, &b);
+  int rc = hd_ista_init(HD_F32, m, n, L, C, seed, trial0, sigma,
+                        grad ? HD_ISTA_GRAD : 0, nullptr, &b);
   if (!rc) rc = hd_ista_run(b, a.data(), th.data(), xs, w, X);
+  if (grad) {
+    void* G = read_file(argv[14], 4 * (size_t)C * n);
+    std::vector<double> gr(2 * (size_t)C * L, 0.0);
+    if (!rc)
+      rc = hd_ista_grad(b, a.data(), th.data(), G, gr.data(),
+                        gr.data() + (size_t)C * L);
+    write_file(argv[15], gr.data(), gr.size() * sizeof(double));
+    std::free(G);
+  }
   const int st = rc ? 0 : hd_ista_status(b);
   write_file(argv[13], X, xb);
   std::printf("rc %d status %d\n", rc, st);
@@ -138,7 +152,8 @@ static int crun_main(char** argv) {
 }
 
 int main(int argc, char** argv) {
-  if (argc == 14 && std::string(argv[1]) == "ista") return ista_main(argv);
+  if ((argc == 14 || argc == 16) && std::string(argv[1]) == "ista")
+    return ista_main(argv);
   if (argc == 12 && std::string(argv[1]) == "cplx") return cplx_main(argv);
   if (argc == 11 && std::string(argv[1]) == "crun") return crun_main(argv);
   if (argc != 14) {

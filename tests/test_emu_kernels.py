@@ -108,37 +108,47 @@ def test_gaussian_alternating_four_chunks_emulated(driver, tmp_path):
 
 def test_ista_batch_emulated(driver, tmp_path):
     """Three lockstep unrolled-ISTA trials (m = 150, n = 300, 4 layers,
-    FP32) against the oracle's single-trial runs with the same keys."""
+    FP32) and their reverse pass against the oracle's single-trial runs with
+    the same keys."""
     C, n, m, L, seed, trial0 = 3, 300, 150, 4, 5, 10
     sig = 1.0 / np.sqrt(m)
+    a32, t32 = float(np.float32(0.3)), float(np.float32(0.6))
     xs = np.stack([inputs.sparse_target(n, 0.8, 2.0, seed=0, trial=i)
                    for i in range(C)]).astype(np.float32)
     w = np.stack([inputs.noise(m, 0.1, seed=0, trial=i)
                   for i in range(C)]).astype(np.float32)
-    xf, wf, out = (str(tmp_path / f) for f in ("xs.bin", "w.bin", "X.bin"))
+    g = np.random.default_rng(3).standard_normal((C, n)).astype(np.float32)
+    xf, wf, out, gf, gout = (str(tmp_path / f) for f in
+                             ("xs.bin", "w.bin", "X.bin", "g.bin", "gr.bin"))
     xs.tofile(xf)
     w.tofile(wf)
+    g.tofile(gf)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     r = subprocess.run([driver, "ista", str(m), str(n), str(L), str(C),
                         str(seed), str(trial0), "%.17g" % sig, "0.3", "0.6", xf,
-                        wf, out], env=env, capture_output=True, text=True,
-                       timeout=600)
+                        wf, out, gf, gout], env=env, capture_output=True,
+                       text=True, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr[-4000:]
     assert "ERROR: AddressSanitizer" not in r.stderr
     assert "runtime error" not in r.stderr
     assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
     X = np.fromfile(out, dtype=np.float32).reshape(C, L + 1, n)
-    worst = 0.0
+    gr = np.fromfile(gout, dtype=np.float64).reshape(2, C, L)
+    worst = worst_g = 0.0
     for i in range(C):
-        orc = oracle.HDOracle(oracle.GINIBRE, n, m=m, tmax=2 * L + 1,
+        orc = oracle.HDOracle(oracle.GINIBRE, n, m=m, tmax=4 * L - 1,
                               seed=seed, trial=trial0 + i, sigma=sig)
         y = orc.mv(xs[i].astype(np.float64)) + w[i]
-        Xo, _, _ = oracle.lista_forward(orc, np.zeros(n), y, [0.3] * L,
-                                        [0.6] * L)
+        Xo, Uo, Vo = oracle.lista_forward(orc, np.zeros(n), y, [a32] * L,
+                                          [t32] * L)
         worst = max(worst, max(relerr(a, b) for a, b in zip(X[i][1:],
                                                             Xo[1:])))
-    print("emulated ISTA batch: %.2e" % worst)
-    assert worst < 1e-4
+        da, dth, _ = oracle.lista_backward(orc, g[i].astype(np.float64),
+                                           [a32] * L, [t32] * L, Uo, Vo)
+        worst_g = max(worst_g, relerr(gr[0, i], da), relerr(gr[1, i], dth))
+    print("emulated ISTA batch: layers %.2e, gradients %.2e"
+          % (worst, worst_g))
+    assert worst < 1e-4 and worst_g < 1e-4
 
 
 def _crun_queries(driver, tmp_path, ens, m, n, f64, sigma, pattern, xs):

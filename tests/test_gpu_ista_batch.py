@@ -128,3 +128,67 @@ def test_lasso_mse_matches_direct_method():
     assert mh[-1] < 0.85 * mh[0]         # ISTA reduces the error
     assert z.max() < 4.5
     assert ks > 1e-3
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11),
+                                       (torch.float32, 1e-4)])
+def test_ista_batch_gradient(dtype, tol):
+    """The batched reverse pass (hd_ista_grad): every trial's dL/da and
+    dL/dtheta against the oracle's reverse pass on the same key and against
+    a separate single-trial handle (hd_lista_backward), and the autograd
+    Function's gradient as the sum over the trials.  (Finite differences
+    need the perturbed forward passes on the same fixed Q, i.e. further
+    queries on one handle, which a batch that restarts its matrices at every
+    run cannot do; the single-trial path checks them, and the batch
+    reproduces its gradients trial by trial.)"""
+    C, n, L, seed, trial0 = 4, 1000, 10, 7, 30
+    m = n // 2
+    sig = 1.0 / np.sqrt(m)
+    xs, w = inputs.lasso_batch(C, n, m, 1 - RHO, SIG_S, SIG_W, seed=seed)
+    xs = torch.from_numpy(xs).to(DEV, dtype)
+    w = torch.from_numpy(w).to(DEV, dtype)
+    rng = np.random.default_rng(1)
+    a = [float(np.float32(v)) for v in 0.3 + 0.02 * rng.standard_normal(L)]
+    th = [float(np.float32(v)) for v in 0.6 + 0.02 * rng.standard_normal(L)]
+    B = hd.IstaBatch(m, n, L, C, seed=seed, trial0=trial0, sigma=sig,
+                     dtype=dtype, device=DEV, grad=True)
+    X = B.run(a, th, xs, w)
+    G = 2.0 * (X[:, -1] - xs)
+    ga, gt, _ = B.grad(a, th, G)
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    ga, gt = ga.cpu().numpy(), gt.cpu().numpy()
+    Xh, Gh = X.double().cpu().numpy(), G.double().cpu().numpy()
+    xh, wh = xs.double().cpu().numpy(), w.double().cpu().numpy()
+    worst = worst_h = 0.0
+    for i in range(C):
+        orc = oracle.HDOracle(oracle.GINIBRE, n, m=m, tmax=4 * L - 1,
+                              seed=seed, trial=trial0 + i, sigma=sig)
+        y = orc.mv(xh[i]) + wh[i]
+        Xo, Uo, Vo = oracle.lista_forward(orc, np.zeros(n), y, a, th)
+        da, dth, _ = oracle.lista_backward(orc, Gh[i], a, th, Uo, Vo)
+        worst = max(worst, relerr(ga[i], da), relerr(gt[i], dth))
+        # a separate handle with the same key
+        A = hd.LazyMatrix(hd.GINIBRE, n, m=m, t_max=4 * L - 1, seed=seed,
+                          trial=trial0 + i, sigma=sig, dtype=dtype,
+                          device=DEV)
+        yd = A.mv(xs[i]) + w[i]
+        Xs, Us, Vs = A.lista_forward(a, th, torch.zeros(n, dtype=dtype,
+                                                        device=DEV), yd)
+        sa, st, _ = A.lista_backward(a, th, Us, Vs, G[i])
+        worst_h = max(worst_h, relerr(ga[i], sa.cpu().numpy()),
+                      relerr(gt[i], st.cpu().numpy()))
+    print("ISTA batch gradient %s: vs oracle %.2e, vs separate handles %.2e"
+          % (dtype, worst, worst_h))
+    assert worst < tol and worst_h < tol
+    if dtype != torch.float64:
+        return
+    # autograd over the batch: the gradient sums the trials'
+    at = torch.tensor(a, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    out = hd.ista_batch(at, tt, B, xs, w)
+    loss = ((out - xs) ** 2).sum()
+    loss.backward()
+    assert np.allclose(at.grad.numpy(), ga.sum(0), rtol=1e-12, atol=0)
+    assert np.allclose(tt.grad.numpy(), gt.sum(0), rtol=1e-12, atol=0)
+
