@@ -368,14 +368,14 @@ struct IstaAdjArgs {
 };
 
 // Phases of one query for all trials; each returns 0 or a HIP error.
-int launch_ista_tdot(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s);
+int launch_ista_tdot(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s);
 int launch_ista_small(int f64, int phase, int side, int ntrials,
                       const IstaTrialDev* d, IstaStep st, hipStream_t s);
-int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s);
-int launch_ista_rand(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s);
+int launch_ista_data(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s);
+int launch_ista_rand(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s);
 int launch_ista_adj(int f64, int ntrials, const IstaAdjArgs& a,
                     hipStream_t s);
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -32,7 +33,8 @@ struct hd_ista_ctx {
   double* adj_part = nullptr;
   int nwg_adj;     // 256-row workgroups over n (reverse-pass reductions)
   int64_t dim[2];  // n (side R), m (side L)
-  int nwg[2];      // workgroups of 256 rows per side
+  int cpt[2];      // 256-row chunks per workgroup, per side
+  int nwg[2];      // workgroups per trial and side
   IstaTrialDev* dev = nullptr;
   char* arena = nullptr;
   CopyJob* jobs = nullptr;  // pi[0] = 1 on both sides and sigma, per trial
@@ -63,6 +65,24 @@ int ifail(hipError_t e) {
   } while (0)
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Chunks of 256 rows per workgroup for a side of `dim` rows: the largest of
+// 4, 2, 1 whose padding stays within 1/16 of the one-chunk rows (a whole
+// trial side then takes few workgroups, each with longer sweeps and fewer
+// reductions per row).  HD_ISTA_CPT = 1, 2 or 4 overrides it.
+int ista_cpt(int64_t dim) {
+  const char* e = std::getenv("HD_ISTA_CPT");
+  if (e) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) return v;
+  }
+  const int64_t base = (dim + 255) / 256 * 256;
+  for (int c = 4; c > 1; c /= 2) {
+    const int64_t q = 256 * (int64_t)c;
+    if ((dim + q - 1) / q * q * 16 <= base * 17) return c;
+  }
+  return 1;
+}
 
 void release(hd_ista_ctx* b) {
   (void)hipStreamSynchronize(b->stream);
@@ -149,12 +169,15 @@ int ista_query(hd_ista_ctx* b, IstaStep& st, int ds) {
   st.kL = b->kL;
   st.step = (uint32_t)(st.q + 1);
   if (b->kR + b->kL > 0) {
-    ILCHK(launch_ista_tdot(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
+    ILCHK(launch_ista_tdot(f64, b->cpt[ds], ds, C * b->nwg[ds], b->dev, st,
+                           b->stream));
     ILCHK(launch_ista_small(f64, 0, ds, C, b->dev, st, b->stream));
   }
-  ILCHK(launch_ista_data(f64, ds, C * b->nwg[ds], b->dev, st, b->stream));
+  ILCHK(launch_ista_data(f64, b->cpt[ds], ds, C * b->nwg[ds], b->dev, st,
+                         b->stream));
   ILCHK(launch_ista_small(f64, 1, ds, C, b->dev, st, b->stream));
-  ILCHK(launch_ista_rand(f64, gs, C * b->nwg[gs], b->dev, st, b->stream));
+  ILCHK(launch_ista_rand(f64, b->cpt[gs], gs, C * b->nwg[gs], b->dev, st,
+                         b->stream));
   if (ds == 0)
     ++b->kR;
   else
@@ -196,8 +219,10 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
   b->dim[1] = m;
   int64_t ld[2];
   for (int s = 0; s < 2; ++s) {
-    ld[s] = (b->dim[s] + 255) / 256 * 256;
-    b->nwg[s] = (int)(ld[s] / 256);
+    b->cpt[s] = ista_cpt(b->dim[s]);
+    const int64_t rows = 256 * (int64_t)b->cpt[s];
+    ld[s] = (b->dim[s] + rows - 1) / rows * rows;
+    b->nwg[s] = (int)(ld[s] / rows);
   }
   const int tm = cv[0], Q = grad ? 4 * L - 1 : 2 * L + 1;
   const int slot2 = Q + 1, extra = slot2 + tm + 1;

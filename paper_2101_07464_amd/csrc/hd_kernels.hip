@@ -1182,7 +1182,7 @@ __device__ __forceinline__ const void* ista_input(const IstaTrialDev& d,
   return ista_row<T>(st, n, trial, (st.q - 1) / 2);
 }
 
-template <typename T>
+template <typename T, int CPT>
 __global__ __launch_bounds__(kWG) void k_ista_tdot(const IstaTrialDev* D,
                                                    int ds, IstaStep st) {
   const int nwg = D[0].s[ds].nwg;
@@ -1192,10 +1192,10 @@ __global__ __launch_bounds__(kWG) void k_ista_tdot(const IstaTrialDev* D,
   a.ncols = ds == 0 ? st.kR : st.kL;
   a.ncols2 = ds == 0 ? st.kL : st.kR;
   a.b = ista_input<T>(d, trial, ds, st);
-  tdot_body<T, 1, false, false>(a, blockIdx.x % nwg);
+  tdot_body<T, CPT, false, false>(a, blockIdx.x % nwg);
 }
 
-template <typename T>
+template <typename T, int CPT>
 __global__ __launch_bounds__(kWG) void k_ista_data(const IstaTrialDev* D,
                                                    int ds, IstaStep st) {
   const int nwg = D[0].s[ds].nwg;
@@ -1210,10 +1210,10 @@ __global__ __launch_bounds__(kWG) void k_ista_data(const IstaTrialDev* D,
   a.pf_step = st.step + 1;
   a.pf_cut = kD;
   a.cslot = kD > 0 ? a.cslot : -1;
-  pass_body<T, 1, kPassData>(a, blockIdx.x % nwg);
+  pass_body<T, CPT, kPassData>(a, blockIdx.x % nwg);
 }
 
-template <typename T>
+template <typename T, int CPT>
 __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
                                                    int gs, IstaStep st) {
   const int nwg = D[0].s[gs].nwg;
@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
     a.dyn.x = ista_row<T>(st, n, trial, t - 1);
     a.dyn.xnext = ista_row<T>(st, n, trial, t);
   }
-  gin_pass_body<T, 1>(a, blockIdx.x % nwg);
+  gin_pass_body<T, CPT>(a, blockIdx.x % nwg);
 }
 
 // One workgroup per trial: the fixed-order sums of its partial rows, then
@@ -1643,15 +1643,28 @@ int launch_prefetch1_batch(int f64, int cpt, int nblk, const TrialDev* d,
   return 0;
 }
 
-int launch_ista_tdot(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s) {
+int launch_ista_tdot(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s) {
   if (nblk <= 0) return 0;
-  if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_tdot<double>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_tdot<float>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
+#define HD_ISTA_LAUNCH(T, C)                                              \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_tdot<T, C>), dim3(nblk), dim3(kWG), \
+                     0, s, d, side, st)
+  if (f64) {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(double, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(double, 2);
+    else
+      HD_ISTA_LAUNCH(double, 1);
+  } else {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(float, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(float, 2);
+    else
+      HD_ISTA_LAUNCH(float, 1);
+  }
+#undef HD_ISTA_LAUNCH
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -1678,15 +1691,28 @@ int launch_ista_small(int f64, int phase, int side, int ntrials,
   return 0;
 }
 
-int launch_ista_data(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s) {
+int launch_ista_data(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s) {
   if (nblk <= 0) return 0;
-  if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<double>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<float>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
+#define HD_ISTA_LAUNCH(T, C)                                              \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_data<T, C>), dim3(nblk), dim3(kWG), \
+                     0, s, d, side, st)
+  if (f64) {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(double, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(double, 2);
+    else
+      HD_ISTA_LAUNCH(double, 1);
+  } else {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(float, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(float, 2);
+    else
+      HD_ISTA_LAUNCH(float, 1);
+  }
+#undef HD_ISTA_LAUNCH
   HD_CHECK_LAUNCH();
   return 0;
 }
@@ -1706,15 +1732,28 @@ int launch_ista_adj(int f64, int ntrials, const IstaAdjArgs& a,
   return 0;
 }
 
-int launch_ista_rand(int f64, int side, int nblk, const IstaTrialDev* d,
-                     IstaStep st, hipStream_t s) {
+int launch_ista_rand(int f64, int cpt, int side, int nblk,
+                     const IstaTrialDev* d, IstaStep st, hipStream_t s) {
   if (nblk <= 0) return 0;
-  if (f64)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_rand<double>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_rand<float>), dim3(nblk),
-                       dim3(kWG), 0, s, d, side, st);
+#define HD_ISTA_LAUNCH(T, C)                                              \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ista_rand<T, C>), dim3(nblk), dim3(kWG), \
+                     0, s, d, side, st)
+  if (f64) {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(double, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(double, 2);
+    else
+      HD_ISTA_LAUNCH(double, 1);
+  } else {
+    if (cpt == 4)
+      HD_ISTA_LAUNCH(float, 4);
+    else if (cpt == 2)
+      HD_ISTA_LAUNCH(float, 2);
+    else
+      HD_ISTA_LAUNCH(float, 1);
+  }
+#undef HD_ISTA_LAUNCH
   HD_CHECK_LAUNCH();
   return 0;
 }
