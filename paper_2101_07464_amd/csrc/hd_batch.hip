@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -69,6 +70,20 @@ int bfail(hipError_t e) {
   } while (0)
 
 size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Chunks of 256 rows per workgroup for every trial of a batch (panels are
+// padded to 1024 rows, so 1, 2 and 4 all tile them).  Four: a batch has
+// workgroups to spare, so longer sweeps with fewer reductions per row win
+// (4096 ragged Haar trials of 1e3..1e5 rows: 1717, 1520 and 1429 ms per run
+// at 1, 2 and 4).  HD_BATCH_CPT = 1, 2 or 4 overrides it.
+int batch_cpt() {
+  const char* e = std::getenv("HD_BATCH_CPT");
+  if (e) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) return v;
+  }
+  return 4;
+}
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 int launch_run(hd_batch_ctx* b, bool copy_out);
@@ -159,7 +174,7 @@ int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
   b->es = b->f64 ? 8 : 4;
   b->stream = (hipStream_t)stream;
   b->count = count;
-  b->cpt = 1;
+  b->cpt = batch_cpt();
   // run order: longest trial first, so the running trials are a prefix
   b->order.resize(count);
   std::iota(b->order.begin(), b->order.end(), 0);

@@ -19,6 +19,11 @@
 //   back (interleaved complex, storage type), OUT receives the answers.
 // usage: driver crun N T A B F64 SEED TRIAL X1_FILE OUT_PREFIX
 //   a complex Haar trajectory (hd_crun); writes OUT_PREFIX.X and .Y.
+// usage: driver batch SPEC_FILE X1_FILE OUT
+//   a batch of FP32 Haar trials (hd_batch_run, tanh(2y), Q-queries): SPEC_FILE
+//   holds int64 pairs (n, T) per trial (seed 0, trial = index); X1_FILE the
+//   x_1 of every trial back to back; OUT receives every trial's
+//   trajectory (T + 1) x n back to back.
 #include "hd_api.hip"
 
 #include <cstdio>
@@ -151,7 +156,53 @@ static int crun_main(char** argv) {
   return rc ? 1 : 0;
 }
 
+static int batch_main(char** argv) {
+  FILE* f = std::fopen(argv[2], "rb");
+  std::vector<int64_t> spec;
+  int64_t v;
+  while (f && std::fread(&v, sizeof(v), 1, f) == 1) spec.push_back(v);
+  if (f) std::fclose(f);
+  const int count = (int)(spec.size() / 2);
+  std::vector<hd_batch_trial> tr(count);
+  size_t xin = 0, xout = 0;
+  for (int i = 0; i < count; ++i) {
+    tr[i].n = spec[2 * i];
+    tr[i].T = (int32_t)spec[2 * i + 1];
+    tr[i].seed = 0;
+    tr[i].trial = (uint32_t)i;
+    xin += (size_t)tr[i].n;
+    xout += (size_t)tr[i].n * (tr[i].T + 1);
+  }
+  float* x1 = (float*)read_file(argv[3], 4 * xin);
+  float* X = (float*)std::calloc(xout, 4);
+  std::vector<const void*> px(count);
+  std::vector<void*> ptx(count);
+  size_t oi = 0, oo = 0;
+  for (int i = 0; i < count; ++i) {
+    px[i] = x1 + oi;
+    ptx[i] = X + oo;
+    oi += (size_t)tr[i].n;
+    oo += (size_t)tr[i].n * (tr[i].T + 1);
+  }
+  hd_batch b = nullptr;
+  int rc = hd_batch_init(HD_F32, tr.data(), count, nullptr, &b);
+  hd_dynamics dyn;
+  dyn.kind = HD_DYN_TANH;
+  dyn.pattern = HD_PATTERN_Q;
+  dyn.a = 2.0;
+  dyn.b = 0.0;
+  if (!rc) rc = hd_batch_run(b, &dyn, px.data(), nullptr, ptx.data(), nullptr);
+  const int st = rc ? 0 : hd_batch_status(b);
+  write_file(argv[4], X, 4 * xout);
+  std::printf("rc %d status %d\n", rc, st);
+  hd_batch_free(b);
+  std::free(x1);
+  std::free(X);
+  return rc ? 1 : 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 5 && std::string(argv[1]) == "batch") return batch_main(argv);
   if ((argc == 14 || argc == 16) && std::string(argv[1]) == "ista")
     return ista_main(argv);
   if (argc == 12 && std::string(argv[1]) == "cplx") return cplx_main(argv);

@@ -14,8 +14,10 @@ runs here through exactly the launches hd_run would issue for it (Haar,
 n = 4099, T = 30, FP32, the case of that fault): it must be clean under both
 sanitizers and agree with the FP64 oracle.  A Gaussian trajectory with Q and
 Q' alternating in the four-chunk launch shape covers the other ensemble and
-the row-split column dots, and a small batch of unrolled-ISTA trials the
-lockstep Gaussian batch.  The complex path (Sec. 3.4) runs mixed Q / Q^H
+the row-split column dots, a small batch of unrolled-ISTA trials the
+lockstep Gaussian batch and its reverse pass, and four ragged Haar trials the
+Haar batch in one and four chunks per workgroup.  The complex path
+(Sec. 3.4) runs mixed Q / Q^H
 sequences with a zero query on U(n) and on a rectangular complex Ginibre
 matrix, GUE steps, and a fused FP32 Haar trajectory.
 """
@@ -45,6 +47,7 @@ def driver(tmp_path_factory):
            "-I", os.path.join(EMU, "shim"), "-I", os.path.join(ROOT, "include"),
            "-I", CSRC, "-x", "c++", os.path.join(EMU, "driver.cpp"),
            "-x", "c++", os.path.join(CSRC, "hd_ista.hip"),
+           "-x", "c++", os.path.join(CSRC, "hd_batch.hip"),
            "-x", "c++", os.path.join(CSRC, "hd_kernels.hip"),
            "-x", "c++", os.path.join(CSRC, "hd_cplx.hip"),
            "-x", "c++", os.path.join(EMU, "emu.cpp"), "-o", out]
@@ -213,3 +216,34 @@ def test_complex_haar_trajectory_emulated(driver, tmp_path):
     for t in range(T):
         assert relerr(Y[t], orc.mv(X[t])) < 1e-5
         assert np.abs(oracle.f_ctanh(Y[t], X[t], a, b) - X[t + 1]).max() < 1e-6
+
+
+@pytest.mark.parametrize("cpt", ["1", "4"])
+def test_haar_batch_emulated(driver, tmp_path, cpt):
+    """Four ragged FP32 Haar trials in one batch (hd_batch_run, tanh(2y)),
+    one and four chunks per workgroup: every x_{t+1} equals the map of the
+    oracle's answer to the emulated run's own x_t."""
+    spec = [(1500, 9), (3000, 5), (700, 12), (2049, 7)]
+    sf, xf, out = (str(tmp_path / f) for f in ("spec.bin", "x1.bin", "X.bin"))
+    np.array(spec, dtype=np.int64).ravel().tofile(sf)
+    np.concatenate([inputs.x1_normal(n, seed=0, trial=i).astype(np.float32)
+                    for i, (n, T) in enumerate(spec)]).tofile(xf)
+    env = dict(os.environ, HD_BATCH_CPT=cpt,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([driver, "batch", sf, xf, out], env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    assert r.stdout.split() == ["rc", "0", "status", "0"], r.stdout
+    X = np.fromfile(out, dtype=np.float32).astype(np.float64)
+    o, worst = 0, 0.0
+    for i, (n, T) in enumerate(spec):
+        Xi = X[o:o + n * (T + 1)].reshape(T + 1, n)
+        o += n * (T + 1)
+        orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=0, trial=i)
+        for t in range(T):
+            worst = max(worst, np.abs(np.tanh(2 * orc.mv(Xi[t])) -
+                                      Xi[t + 1]).max())
+    assert worst < 1e-6
