@@ -638,6 +638,30 @@ LASSO = dict(name="lasso_ista_n1000_m500_T50_trials1e5_fp32", n=1000, m=500,
              sig_w=0.1, direct_trials=20_000)
 
 
+def ista_batch_bytes(n, m, L, es=4):
+    """Algorithmic bytes of one trial of an ISTA batch run (2L + 1 queries):
+    per query the TDOT streams the data side's reflector and basis columns
+    and reads its input, the data pass streams the reflector columns, reads
+    the input and writes the new column, the random pass streams the random
+    side's reflector and basis columns and reads/writes its vectors."""
+    dim = (n, m)
+    kR = kL = 0
+    total = 0
+    for q in range(2 * L + 1):
+        ds = 0 if (q == 0 or q % 2 == 1) else 1
+        gs = 1 - ds
+        kD, kG = (kR, kL) if ds == 0 else (kL, kR)
+        if kR + kL > 0:
+            total += (kD + kG + 1) * dim[ds]
+        total += (kD + 2) * dim[ds]
+        total += (kG + kD + 3) * dim[gs]
+        if ds == 0:
+            kR += 1
+        else:
+            kL += 1
+    return total * es
+
+
 def main_lasso(args):
     """The lasso experiment of Sec. 2.1 (the paper's first figure): 1e5
     independent trials of ISTA (eq. (ista)) on Gaussian Q (m = n/2,
@@ -713,7 +737,16 @@ def main_lasso(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": c["name"], "n": n, "m": m, "layers": L,
-                   "trials": C, "queries_per_trial": 2 * L},
+                   "trials": C, "queries_per_trial": 2 * L + 1},
+        "roofline": {"bound": "hbm", "kernel": "whole batched step",
+                     "achieved": C * ista_batch_bytes(n, m, L) /
+                     (elapsed / args.steps) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": C * ista_batch_bytes(n, m, L) /
+                     (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "algorithmic_bytes_per_step":
+                         C * ista_batch_bytes(n, m, L)},
         "mse_curve": {"hd": [round(float(v), 6) for v in e_hd],
                       "direct": [round(float(v), 6) for v in e_dir],
                       "max_abs_diff": float(np.max(np.abs(e_hd - e_dir))),
