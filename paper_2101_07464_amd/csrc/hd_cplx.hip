@@ -36,9 +36,10 @@
 // Every panel kernel is row-split: a thread owns four rows (strided by 64, so
 // each load instruction of a wave covers 64 consecutive complex entries);
 // dots are summed over the wave with the reduce-scatter of hd_device.hpp and
-// written as per-wave partial rows, which k_cx_reduce sums in a fixed order.
+// written as per-wave partial rows, which k_cx_reduce1/2 sum in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -404,14 +405,16 @@ struct RedJob {
   int pstride;
   int start[3], count[3];  // slot ranges
   double* out;             // out[slot] = sum over rows of part[row][slot]
+  double* stage;           // block partials of the first stage
 };
 
-__global__ __launch_bounds__(kWG) void k_cx_reduce(RedJob a, RedJob b) {
-  __shared__ double scr[kWaves];
-  const int na = a.count[0] + a.count[1] + a.count[2];
-  const bool first = (int)blockIdx.x < na;
-  const RedJob& j = first ? a : b;
-  int q = first ? (int)blockIdx.x : (int)blockIdx.x - na;
+constexpr int kRedRows = 256;  // rows per block of the first stage
+constexpr int kRedSlots = 32;  // slots per block of the first stage
+
+__device__ __forceinline__ int red_slots(const RedJob& j) {
+  return j.count[0] + j.count[1] + j.count[2];
+}
+__device__ __forceinline__ int red_slot(const RedJob& j, int q) {
   int slot = -1;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -422,11 +425,61 @@ __global__ __launch_bounds__(kWG) void k_cx_reduce(RedJob a, RedJob b) {
         q -= j.count[r];
     }
   }
+  return slot;
+}
+__device__ __forceinline__ int red_blocks(const RedJob& j) {
+  return red_slots(j) ? (int)((j.nrows + kRedRows - 1) / kRedRows) : 0;
+}
+
+__device__ __forceinline__ int red_groups(const RedJob& j) {
+  return (red_slots(j) + kRedSlots - 1) / kRedSlots;
+}
+
+// Two-stage fixed-order sums of the partial rows.  Stage 1: a block takes R
+// rows and 32 consecutive slots of one job; its 8 x 32 threads sum rows
+// r = rl, rl + 8, ... (each row read as a contiguous run of slots), then
+// the 8 row lanes are added in order.  Stage 2: one thread per slot adds the
+// row blocks in order.
+__global__ __launch_bounds__(kWG) void k_cx_reduce1(RedJob a, RedJob b) {
+  __shared__ double lds[kWG];
+  const int na = red_blocks(a) * red_groups(a);
+  const bool first = (int)blockIdx.x < na;
+  const RedJob& j = first ? a : b;
+  const int id = first ? (int)blockIdx.x : (int)blockIdx.x - na;
+  const int ng = red_groups(j);
+  const int blk = id / ng, sg = id % ng;
+  const int ns = red_slots(j);
+  const int sl = threadIdx.x % kRedSlots, rl = threadIdx.x / kRedSlots;
+  const int q = sg * kRedSlots + sl;
+  const int64_t r0 = (int64_t)blk * kRedRows;
+  const int64_t r1 = r0 + kRedRows < j.nrows ? r0 + kRedRows : j.nrows;
   double s = 0.0;
-  for (int64_t r = threadIdx.x; r < j.nrows; r += kWG)
-    s += j.part[r * j.pstride + slot];
-  s = block_sum(s, scr);
-  if (threadIdx.x == 0) j.out[slot] = s;
+  if (q < ns) {
+    const int slot = red_slot(j, q);
+#pragma unroll 8
+    for (int64_t r = r0 + rl; r < r1; r += kWG / kRedSlots)
+      s += j.part[r * j.pstride + slot];
+  }
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  if (rl == 0 && q < ns) {
+    double t = 0.0;
+    for (int k = 0; k < kWG / kRedSlots; ++k) t += lds[k * kRedSlots + sl];
+    j.stage[(int64_t)blk * ns + q] = t;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_cx_reduce2(RedJob a, RedJob b) {
+  const int sa = red_slots(a);
+  const int q0 = blockIdx.x * kWG + threadIdx.x;
+  if (q0 >= sa + red_slots(b)) return;
+  const bool first = q0 < sa;
+  const RedJob& j = first ? a : b;
+  const int q = first ? q0 : q0 - sa;
+  const int ns = red_slots(j), nb = red_blocks(j);
+  double s = 0.0;
+  for (int k = 0; k < nb; ++k) s += j.stage[(int64_t)k * ns + q];
+  j.out[red_slot(j, q)] = s;
 }
 
 // ------------------------------------------------------------ L2 / L3 ----
@@ -822,6 +875,7 @@ struct hd_cctx {
   int64_t dim[2];
   int nwg[2];
   double* part[2];
+  double* stage[2];  // first-stage partials of the two jobs of a reduction
   int pstride;
   RedLay rl;
   CoefLay cl;
@@ -953,11 +1007,23 @@ int launch_dots(hd_cctx* h, const DotsJob& a, const DotsJob& b) {
   return HD_OK;
 }
 
-int launch_reduce(hd_cctx* h, const RedJob& a, const RedJob& b) {
-  const int grid = a.count[0] + a.count[1] + a.count[2] + b.count[0] +
-                   b.count[1] + b.count[2];
-  if (grid == 0) return HD_OK;
-  hipLaunchKernelGGL(k_cx_reduce, dim3(grid), dim3(kWG), 0, h->stream, a, b);
+int launch_reduce(hd_cctx* h, RedJob a, RedJob b) {
+  auto slots = [](const RedJob& j) {
+    return j.count[0] + j.count[1] + j.count[2];
+  };
+  auto blocks = [&](const RedJob& j) {
+    const int rows = slots(j) ? (int)((j.nrows + kRedRows - 1) / kRedRows) : 0;
+    return rows * ((slots(j) + kRedSlots - 1) / kRedSlots);
+  };
+  const int ns = slots(a) + slots(b);
+  if (ns == 0) return HD_OK;
+  a.stage = h->stage[0];
+  b.stage = h->stage[1];
+  hipLaunchKernelGGL(k_cx_reduce1, dim3(blocks(a) + blocks(b)), dim3(kWG), 0,
+                     h->stream, a, b);
+  CXHIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cx_reduce2, dim3((ns + kWG - 1) / kWG), dim3(kWG), 0,
+                     h->stream, a, b);
   CXHIP(hipGetLastError());
   return HD_OK;
 }
@@ -1259,6 +1325,16 @@ int hd_cinit(int32_t ensemble, int32_t storage, int64_t m, int64_t n,
     CXA(S.ref, sizeof(double) * kRefStride * (size_t)kmax);
     CXA(S.del, sizeof(double) * 2 * (size_t)kmax);
     CXA(h->part[s], sizeof(double) * (size_t)h->pstride * h->nwg[s] * kWaves);
+  }
+  {
+    // first-stage partials: at most (rows / kRedRows) blocks x pstride slots
+    int64_t rows = 0;
+    for (int s = 0; s < 2; ++s)
+      rows = std::max(rows, (int64_t)h->nwg[s] * kWaves);
+    const size_t sb = sizeof(double) * (size_t)h->pstride *
+                      (size_t)((rows + kRedRows - 1) / kRedRows);
+    CXA(h->stage[0], sb);
+    CXA(h->stage[1], sb);
   }
   CXA(h->red, sizeof(double) * (size_t)h->rl.end);
   CXA(h->coef, sizeof(double) * (size_t)h->cl.end);
