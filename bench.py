@@ -103,21 +103,25 @@ KERNEL_OF_KIND = {(0, "ginibre"): "k_tdot", (1, "ginibre"): "k_pass<data>",
                   (1, "haar"): "k_pass<data>", (2, "haar"): "k_pass<random>"}
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(files=("hd_kernels.hip", "hd_device.hpp",
+                                 "hd_internal.hpp")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("hd_kernels.hip", "hd_device.hpp", "hd_internal.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2101_07464_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload, kernel):
+CPLX_SOURCES = ("hd_cplx.hip", "hd_device.hpp", "hd_internal.hpp")
+
+
+def measured_traffic(workload, kernel, files=None):
     """HBM bytes per launch from a committed PMC summary under profiles/,
     or None when there is none for these kernel sources."""
     import glob
-    sha = kernel_sources_sha256()
+    sha = kernel_sources_sha256(files) if files else kernel_sources_sha256()
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_pmc_traffic.md")):
         kv = {}
         with open(path) as fh:
@@ -823,7 +827,9 @@ def main_cplx(args):
         "roofline": {"bound": "hbm", "kernel": CPLX_KINDS[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "launches": launches,
+                     "traffic": measured_traffic(c["name"], CPLX_KINDS[dom],
+                                                 CPLX_SOURCES),
+                     "launches": launches,
                      "avg_launch_us": ms * 1e3 / max(launches, 1),
                      "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                      "per_kernel": per_kernel},

@@ -469,17 +469,28 @@ __global__ __launch_bounds__(kWG) void k_cx_reduce1(RedJob a, RedJob b) {
   }
 }
 
+// Stage 2: a block takes 32 consecutive slots of one job; its 8 x 32
+// threads add row blocks k = rl, rl + 8, ..., then the 8 row lanes in order.
 __global__ __launch_bounds__(kWG) void k_cx_reduce2(RedJob a, RedJob b) {
-  const int sa = red_slots(a);
-  const int q0 = blockIdx.x * kWG + threadIdx.x;
-  if (q0 >= sa + red_slots(b)) return;
-  const bool first = q0 < sa;
+  __shared__ double lds[kWG];
+  const int ga = red_groups(a);
+  const bool first = (int)blockIdx.x < ga;
   const RedJob& j = first ? a : b;
-  const int q = first ? q0 : q0 - sa;
+  const int sg = first ? (int)blockIdx.x : (int)blockIdx.x - ga;
   const int ns = red_slots(j), nb = red_blocks(j);
+  const int sl = threadIdx.x % kRedSlots, rl = threadIdx.x / kRedSlots;
+  const int q = sg * kRedSlots + sl;
   double s = 0.0;
-  for (int k = 0; k < nb; ++k) s += j.stage[(int64_t)k * ns + q];
-  j.out[red_slot(j, q)] = s;
+  if (q < ns)
+    for (int k = rl; k < nb; k += kWG / kRedSlots)
+      s += j.stage[(int64_t)k * ns + q];
+  lds[threadIdx.x] = s;
+  __syncthreads();
+  if (rl == 0 && q < ns) {
+    double t = 0.0;
+    for (int k = 0; k < kWG / kRedSlots; ++k) t += lds[k * kRedSlots + sl];
+    j.out[red_slot(j, q)] = t;
+  }
 }
 
 // ------------------------------------------------------------ L2 / L3 ----
@@ -1022,8 +1033,10 @@ int launch_reduce(hd_cctx* h, RedJob a, RedJob b) {
   hipLaunchKernelGGL(k_cx_reduce1, dim3(blocks(a) + blocks(b)), dim3(kWG), 0,
                      h->stream, a, b);
   CXHIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cx_reduce2, dim3((ns + kWG - 1) / kWG), dim3(kWG), 0,
-                     h->stream, a, b);
+  const int groups = (slots(a) + kRedSlots - 1) / kRedSlots +
+                     (slots(b) + kRedSlots - 1) / kRedSlots;
+  hipLaunchKernelGGL(k_cx_reduce2, dim3(groups), dim3(kWG), 0, h->stream, a,
+                     b);
   CXHIP(hipGetLastError());
   return HD_OK;
 }
