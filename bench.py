@@ -855,6 +855,39 @@ def main_cplx(args):
     print(json.dumps(out), flush=True)
 
 
+def stream_reference():
+    """What plain streaming kernels reach on the same GPU, as context for
+    the roofline fractions (which are taken against the 8 TB/s peak): a
+    4 GiB float32 copy (torch.mul into another buffer, read + write bytes)
+    and a 4 GiB read-only reduction (torch.sum), best of five each, timed
+    with events on the current stream."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    res = {}
+    for name, fn, nbytes in (
+            ("copy", lambda: torch.mul(src, 1.0, out=dst), 8 * n),
+            ("read", lambda: torch.sum(src), 4 * n)):
+        fn()
+        best = None
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        res[name + "_GBs"] = nbytes / (best * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    res["what"] = ("torch copy and sum of 4 GiB float32 on the same GPU, "
+                   "best of five: the streaming rate plain kernels reach")
+    return res
+
+
 def copy_calibration():
     """A plain device copy of known size (read 1 GiB, write 1 GiB, five
     times) for scaling the PMC byte counters of the panel kernels."""
@@ -1027,6 +1060,8 @@ def run_single(args, wl):
     A.close()
     del A
     torch.cuda.empty_cache()
+    if not args.no_checks:
+        out["roofline"]["stream_reference"] = stream_reference()
     if wl.get("dense", False):
         out["dense_direct"] = dense_direct(wl, x1, args.steps)
         out["vs_dense_direct"] = (out["dense_direct"]["ms_per_step"] /
