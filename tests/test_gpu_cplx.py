@@ -12,6 +12,9 @@ complex FP64 oracle.
   eps_32 sqrt(n) for a generic pivot; 1e-4 leaves a margin of 20 at
   n = 1e5), and the unitary invariants ||y_t|| = ||x_t|| and
   Y^H Y = X^H X over the whole trajectory;
+* FP64 free run of a fused Haar trajectory (whose output passes prepare
+  the next query's draw) against the oracle's own run, and against the same
+  queries one at a time;
 * laws: |Q_11|^2 ~ Beta(1, n - 1) and E Q_11^2 = 0 over many Haar keys;
 * the GUE matrix rebuilt column by column is Hermitian;
 * edge cases: a zero query (identity reflector), capacity, non-finite
@@ -179,3 +182,30 @@ def test_capacity_nonfinite_and_reset():
     y = _host(A.mv(_dev(np.ones(n), torch.complex64)))
     orc = oracle.CHDOracle(oracle.GINIBRE, n, m=5, tmax=10, seed=1, trial=0)
     assert relerr(y, orc.mv(np.ones(n))) < 1e-5
+
+
+def test_fp64_haar_trajectory_free_run():
+    """hd_crun in FP64 (every query but the last prepares the next query's
+    draw inside its output pass) against the oracle's own free run of the
+    same map: every x_t and y_t within 1e-11; and against the same queries
+    issued one at a time (hd_cstep, no lookahead)."""
+    n, T, a, b = 3001, 30, 1.0, 0.1
+    rng = np.random.default_rng(12)
+    x1 = crand(rng, n) / np.sqrt(2)
+    A = hd.CLazyMatrix(hd.HAAR, n, t_max=T, seed=8, trial=4,
+                       dtype=torch.complex128, device=DEV)
+    X, Y = A.run(_dev(x1, torch.complex128), T, a, b)
+    torch.cuda.synchronize()
+    assert A.status() == 0
+    X, Y = _host(X), _host(Y)
+    orc = oracle.CHDOracle(oracle.HAAR, n, tmax=T, seed=8, trial=4)
+    Xo, Yo = oracle.run_ctrajectory(orc, x1, T, a, b)
+    ex = max(relerr(p, q) for p, q in zip(X, Xo))
+    ey = max(relerr(p, q) for p, q in zip(Y, Yo))
+    B = hd.CLazyMatrix(hd.HAAR, n, t_max=T, seed=8, trial=4,
+                       dtype=torch.complex128, device=DEV)
+    es = max(relerr(_host(B.mv(_dev(X[t], torch.complex128))), Y[t])
+             for t in range(T))
+    print("FP64 U(%d) trajectory of %d: x %.2e, y %.2e, step by step %.2e"
+          % (n, T, ex, ey, es))
+    assert ex < 1e-11 and ey < 1e-11 and es < 1e-11
