@@ -262,6 +262,12 @@ def run_batch(args, steps, warmup):
     W = float(sum(nominal_work(n, T) for n, T, _, _ in trials))
     by = sum(batch_bytes(n, T) for n, T, _, _ in trials)
     B = hd.HaarBatch(trials, dtype=torch.float32, device=dev)
+    shape = {"chunks_per_workgroup": B.shape(), "source": "built-in"}
+    if not args.no_autotune:
+        # the library's tuner: one timed run of the whole batch per shape
+        chosen, ms = B.autotune(x1, "tanh", C3["a"], C3["b"], reps=1)
+        shape = {"chunks_per_workgroup": chosen, "source": "hd_batch_autotune",
+                 "ms_per_run": {str(k): round(v, 2) for k, v in ms.items()}}
     for _ in range(warmup):
         B.run(x1, "tanh", C3["a"], C3["b"])
     torch.cuda.synchronize()
@@ -313,12 +319,15 @@ def run_batch(args, steps, warmup):
         "data": "synthetic",
         "config": {"workload": C3["name"], "trials": len(trials),
                    "elem_updates_per_step": W,
-                   "algorithmic_bytes_per_step": by},
+                   "algorithmic_bytes_per_step": by, "launch_shape": shape},
         "roofline": {"bound": "hbm", "kernel": "whole batched step",
                      "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(C3["name"],
-                                                 "whole batched step"),
+                     # counters were taken in the four-chunk shape
+                     "traffic": (measured_traffic(C3["name"],
+                                                  "whole batched step")
+                                 if shape["chunks_per_workgroup"] == 4
+                                 else None),
                      "traffic_unit": "bytes per batched step"},
         "plain_per_trial": {"value": plain, "unit": "elem-updates/s",
                             "sample": "%d of the trials, one handle each "
@@ -1080,6 +1089,7 @@ def extras(args, out):
             "workload": b["config"]["workload"], "value": b["value"],
             "unit": b["unit"], "ms_per_step": b["ms_per_step"],
             "steps": b["steps"], "frac_hbm_whole_step": b["roofline"]["frac"],
+            "launch_shape": b["config"]["launch_shape"],
             "plain_per_trial": b["plain_per_trial"],
             "hipgraph_replay_ms_per_step":
                 b["hipgraph_replay"]["ms_per_step"]}

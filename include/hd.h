@@ -360,6 +360,34 @@ int hd_batch_status(hd_batch b);
  * Errors: HD_ERR_INVALID, HD_ERR_UNSUPPORTED (null stream). */
 int hd_batch_set_graph(hd_batch b, int32_t enable);
 
+/* Launch shape of the batched panel kernels: every workgroup covers
+ * `chunks` (1, 2 or 4) chunks of 256 rows of one trial's panels (panels are
+ * padded to 1024 rows, so every shape tiles every trial).  More chunks mean
+ * longer sweeps and fewer partial rows to reduce; fewer mean more workgroups
+ * in flight.  The initial shape is 4 (environment HD_BATCH_CPT = 1, 2 or 4
+ * overrides it).  The answers do not depend on the shape beyond the order of
+ * the FP64 partial sums.  Synchronises the batch's stream and drops graphs
+ * recorded by hd_batch_set_graph (the next run records anew).
+ * Errors: HD_ERR_INVALID (other values), HD_ERR_HIP. */
+int hd_batch_set_shape(hd_batch b, int32_t chunks);
+
+/* The current shape (1, 2 or 4), or HD_ERR_INVALID for a NULL handle. */
+int hd_batch_shape(hd_batch b);
+
+/* Autotuner for the batch's launch shape: for each shape 1, 2 and 4, one
+ * untimed run and `reps` (1..100) timed runs of the whole batch with the map
+ * dyn and inputs x1 (as hd_batch_run, outputs kept in the batch's own
+ * buffers; HIP events on the batch's stream, direct launches), then installs
+ * the fastest shape if it is at least 3% faster than the initial shape's
+ * default, else that default.  ms: NULL or 3 doubles receiving the mean
+ * milliseconds per run at 1, 2 and 4 chunks; chosen: NULL or the installed
+ * shape.  Blocks until the timed runs end.
+ * Errors: as hd_batch_run and hd_batch_set_shape; HD_ERR_INVALID for reps
+ * out of range. */
+int hd_batch_autotune(hd_batch b, const hd_dynamics* dyn,
+                      const void* const* x1, int32_t reps, double* ms,
+                      int32_t* chosen);
+
 /* Change the stream of later calls. */
 int hd_batch_set_stream(hd_batch b, void* stream);
 

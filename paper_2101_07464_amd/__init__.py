@@ -353,6 +353,32 @@ class HaarBatch:
                                                   1 if enable else 0),
                    "hd_batch_set_graph")
 
+    def set_shape(self, chunks):
+        """Chunks of 256 rows per workgroup of the batched kernels (1, 2, 4;
+        ``hd_batch_set_shape``)."""
+        _lib.check(_lib.load().hd_batch_set_shape(self._h, int(chunks)),
+                   "hd_batch_set_shape")
+
+    def shape(self):
+        return _lib.load().hd_batch_shape(self._h)
+
+    def autotune(self, x1, dyn, a, b, reps=2):
+        """Time whole runs at 1, 2 and 4 chunks per workgroup and install
+        the fastest (``hd_batch_autotune``).  Returns (chosen, {chunks: ms})."""
+        if len(x1) != len(self.trials):
+            raise ValueError("one x1 per trial")
+        x1 = [t.to(self.device, self.dtype).contiguous() for t in x1]
+        L = _lib.load()
+        _lib.check(L.hd_batch_set_stream(self._h, _stream_ptr(self.device)),
+                   "hd_batch_set_stream")
+        d = _lib.HDDynamics(_DYN[dyn], HD_PATTERN_Q, a, b)
+        ms = (ctypes.c_double * 3)()
+        ch = ctypes.c_int32()
+        _lib.check(L.hd_batch_autotune(self._h, ctypes.byref(d),
+                                       self._ptrs(x1), int(reps), ms,
+                                       ctypes.byref(ch)), "hd_batch_autotune")
+        return ch.value, {1: ms[0], 2: ms[1], 4: ms[2]}
+
 
 class IstaBatch:
     """Independent unrolled-ISTA trials on Gaussian matrices of one shape

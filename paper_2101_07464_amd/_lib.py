@@ -40,6 +40,7 @@ EXPORTS = ["hd_init", "hd_free", "hd_step", "hd_apply_T", "hd_status",
            "hd_lista_backward", "hd_autotune", "hd_shape_rule",
            "hd_autotune_clear", "hd_export", "hd_import", "hd_goe_step",
            "hd_usv_step", "hd_batch_set_graph", "hd_run_noalloc",
+           "hd_batch_set_shape", "hd_batch_shape", "hd_batch_autotune",
            "hd_noalloc_scratch_bytes", "hd_spectral_power", "hd_ista_init",
            "hd_ista_run", "hd_ista_grad", "hd_ista_status",
            "hd_ista_set_stream", "hd_ista_free", "hd_cinit", "hd_cstep", "hd_crun",
@@ -121,6 +122,10 @@ def load():
         "hd_goe_step": (i32, [vp, vp, vp]),
         "hd_usv_step": (i32, [vp, vp, vp, i32, vp, vp]),
         "hd_batch_set_graph": (i32, [vp, i32]),
+        "hd_batch_set_shape": (i32, [vp, i32]),
+        "hd_batch_shape": (i32, [vp]),
+        "hd_batch_autotune": (i32, [vp, P(HDDynamics), P(vp), i32,
+                                    P(ctypes.c_double), P(i32)]),
         "hd_import": (i32, [P(HDConfig), vp, ctypes.c_size_t, P(vp)]),
         "hd_run_noalloc": (i32, [P(HDConfig), P(HDDynamics), i32, vp, vp,
                                  vp, vp, vp]),

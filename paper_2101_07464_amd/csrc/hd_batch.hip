@@ -87,6 +87,7 @@ int batch_cpt() {
 int64_t round_up(int64_t v, int64_t q) { return (v + q - 1) / q * q; }
 
 int launch_run(hd_batch_ctx* b, bool copy_out);
+int apply_shape(hd_batch_ctx* b, int cpt);
 
 void release(hd_batch_ctx* b) {
   (void)hipStreamSynchronize(b->stream);
@@ -186,26 +187,25 @@ int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
   b->active.assign(b->tmax + 2, 0);
   for (const auto& t : b->tr)
     for (int s = 1; s <= t.T; ++s) b->active[s]++;
-  // workgroups and arena layout
-  const int rows = 256 * b->cpt;
-  b->blk_first.assign(count + 1, 0);
+  // arena layout; partial rows and the block map are sized for the most
+  // workgroups any shape launches (one chunk per workgroup)
   std::vector<Layout> lay(count);
   std::vector<int> nwg(count), pstride(count), slot2(count), extra(count);
   size_t arena = 0;
   int64_t nmax = 0;
+  int nblk = 0;
   for (int i = 0; i < count; ++i) {
     const auto& t = b->tr[i];
     const int64_t ld = round_up(t.n, kChunk);
-    nwg[i] = (int)(ld / rows);
+    nwg[i] = (int)(ld / 256);
     slot2[i] = t.T + 1;
     extra[i] = slot2[i] + t.T + 1;
     pstride[i] = extra[i] + kNumExtra;
     lay[i] = layout_of(arena, t.n, t.T, b->es, nwg[i], pstride[i]);
     arena = lay[i].end;
-    b->blk_first[i + 1] = b->blk_first[i] + nwg[i];
+    nblk += nwg[i];
     nmax = std::max(nmax, t.n);
   }
-  const int nblk = b->blk_first[count];
   int rc = HD_OK;
 #define BALLOC(ptr, bytes)          \
   do {                              \
@@ -224,10 +224,7 @@ int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
   BALLOC(b->flag, sizeof(int) * 4);
   BALLOC(b->zeros, (size_t)b->es * nmax + 8);
 #undef BALLOC
-  // block map and the pi[0] = 1 entries
-  std::vector<int> bt(nblk);
-  for (int i = 0; i < count; ++i)
-    for (int q = b->blk_first[i]; q < b->blk_first[i + 1]; ++q) bt[q] = i;
+  // the pi[0] = 1 entries
   auto fail = [&](hipError_t e) {
     int r = bfail(e);
     release(b);
@@ -236,17 +233,12 @@ int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
   };
   if (hipStreamSynchronize(b->stream) != hipSuccess)
     return fail(hipGetLastError());
-  hipError_t e = hipMemcpy(b->blk_trial, bt.data(), sizeof(int) * nblk,
-                           hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->blk_first_d, b->blk_first.data(),
-                  sizeof(int) * (count + 1), hipMemcpyHostToDevice);
   // pi[0] = 1 on both sides of every trial: copies of one double kept at the
   // end of the zero vector
   const double one = 1.0;
   double* d_one = (double*)((char*)b->zeros + (size_t)b->es * nmax);
-  if (e == hipSuccess)
-    e = hipMemcpy(d_one, &one, sizeof(double), hipMemcpyHostToDevice);
+  hipError_t e =
+      hipMemcpy(d_one, &one, sizeof(double), hipMemcpyHostToDevice);
   std::vector<CopyJob> pij(2 * (size_t)count);
   for (int i = 0; i < count; ++i)
     for (int s = 0; s < 2; ++s)
@@ -326,12 +318,69 @@ int hd_batch_init(int32_t storage, const hd_batch_trial* trials,
     d.hs.flag = b->flag;
     d.x0 = b->zeros;
     d.T = t.T;
-    d.nwg = nwg[i];
     b->host[i] = d;
     b->ring_off[i] = L.ring;
   }
+  const int rs = apply_shape(b, batch_cpt());
+  if (rs != HD_OK) {
+    release(b);
+    delete b;
+    return rs;
+  }
   *out = b;
   return HD_OK;
+}
+
+int hd_batch_set_shape(hd_batch b, int32_t chunks) {
+  if (!b || (chunks != 1 && chunks != 2 && chunks != 4)) return HD_ERR_INVALID;
+  return chunks == b->cpt ? HD_OK : apply_shape(b, chunks);
+}
+
+int hd_batch_shape(hd_batch b) { return b ? b->cpt : HD_ERR_INVALID; }
+
+int hd_batch_autotune(hd_batch b, const hd_dynamics* dyn,
+                      const void* const* x1, int32_t reps, double* ms,
+                      int32_t* chosen) {
+  if (!b || !dyn || !x1 || reps < 1 || reps > 100) return HD_ERR_INVALID;
+  static const int kShapes[3] = {1, 2, 4};
+  const int builtin = batch_cpt();
+  const bool graph = b->use_graph;
+  b->use_graph = false;
+  double t[3] = {0, 0, 0};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int rc = HD_OK;
+  for (auto& v : ev)
+    if (rc == HD_OK && hipEventCreate(&v) != hipSuccess)
+      rc = bfail(hipGetLastError());
+  for (int i = 0; i < 3 && rc == HD_OK; ++i) {
+    rc = hd_batch_set_shape(b, kShapes[i]);
+    // one untimed run (it also uploads the changed per-trial arguments)
+    if (rc == HD_OK) rc = hd_batch_run(b, dyn, x1, nullptr, nullptr, nullptr);
+    if (rc == HD_OK && hipEventRecord(ev[0], b->stream) != hipSuccess)
+      rc = bfail(hipGetLastError());
+    for (int r = 0; r < reps && rc == HD_OK; ++r)
+      rc = hd_batch_run(b, dyn, x1, nullptr, nullptr, nullptr);
+    float el = 0.f;
+    if (rc == HD_OK && (hipEventRecord(ev[1], b->stream) != hipSuccess ||
+                        hipEventSynchronize(ev[1]) != hipSuccess ||
+                        hipEventElapsedTime(&el, ev[0], ev[1]) != hipSuccess))
+      rc = bfail(hipGetLastError());
+    t[i] = (double)el / reps;
+  }
+  for (auto& v : ev)
+    if (v) (void)hipEventDestroy(v);
+  b->use_graph = graph;
+  if (rc != HD_OK) return rc;
+  // the built-in shape stays unless another is at least 3% faster
+  const int ib = builtin == 1 ? 0 : builtin == 2 ? 1 : 2;
+  int imin = 0;
+  for (int i = 1; i < 3; ++i)
+    if (t[i] < t[imin]) imin = i;
+  const int best = t[imin] < 0.97 * t[ib] ? kShapes[imin] : builtin;
+  if (ms)
+    for (int i = 0; i < 3; ++i) ms[i] = t[i];
+  if (chosen) *chosen = best;
+  return hd_batch_set_shape(b, best);
 }
 
 int hd_batch_set_stream(hd_batch b, void* stream) {
@@ -456,6 +505,34 @@ int hd_batch_set_graph(hd_batch b, int32_t enable) {
 }  // extern "C"
 
 namespace {
+
+// Workgroups of `cpt` chunks for every trial: the block map (workgroup ->
+// trial, each trial's first workgroup) and each trial's partial-row count.
+// Recorded graphs hold the old launch sizes and are dropped.
+int apply_shape(hd_batch_ctx* b, int cpt) {
+  const int C = b->count;
+  std::vector<int> first(C + 1, 0);
+  for (int i = 0; i < C; ++i)
+    first[i + 1] = first[i] + (int)(round_up(b->tr[i].n, kChunk) / (256 * cpt));
+  std::vector<int> bt(first[C]);
+  for (int i = 0; i < C; ++i)
+    for (int q = first[i]; q < first[i + 1]; ++q) bt[q] = i;
+  BHIP(hipStreamSynchronize(b->stream));
+  for (auto& e : b->exec)
+    if (e) {
+      BHIP(hipGraphExecDestroy(e));
+      e = nullptr;
+    }
+  BHIP(hipMemcpy(b->blk_trial, bt.data(), sizeof(int) * bt.size(),
+                 hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(b->blk_first_d, first.data(), sizeof(int) * (C + 1),
+                 hipMemcpyHostToDevice));
+  for (int i = 0; i < C; ++i) b->host[i].nwg = first[i + 1] - first[i];
+  b->blk_first = first;
+  b->cpt = cpt;
+  b->uploaded = false;  // the next run copies the new nwg to the device
+  return HD_OK;
+}
 
 // The launches of one run: x_1 in, every step, x_{T+1} out (when asked).
 int launch_run(hd_batch_ctx* b, bool copy_out) {

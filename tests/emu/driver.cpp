@@ -19,11 +19,13 @@
 //   back (interleaved complex, storage type), OUT receives the answers.
 // usage: driver crun N T A B F64 SEED TRIAL X1_FILE OUT_PREFIX
 //   a complex Haar trajectory (hd_crun); writes OUT_PREFIX.X and .Y.
-// usage: driver batch SPEC_FILE X1_FILE OUT
+// usage: driver batch SPEC_FILE X1_FILE OUT [SHAPES]
 //   a batch of FP32 Haar trials (hd_batch_run, tanh(2y), Q-queries): SPEC_FILE
 //   holds int64 pairs (n, T) per trial (seed 0, trial = index); X1_FILE the
 //   x_1 of every trial back to back; OUT receives every trial's
-//   trajectory (T + 1) x n back to back.
+//   trajectory (T + 1) x n back to back.  With SHAPES (digits 1, 2, 4 and
+//   'a'): one run per digit after hd_batch_set_shape, written to OUT.0,
+//   OUT.1, ...; 'a' runs hd_batch_autotune.
 #include "hd_api.hip"
 
 #include <cstdio>
@@ -156,7 +158,7 @@ static int crun_main(char** argv) {
   return rc ? 1 : 0;
 }
 
-static int batch_main(char** argv) {
+static int batch_main(char** argv, const char* shapes) {
   FILE* f = std::fopen(argv[2], "rb");
   std::vector<int64_t> spec;
   int64_t v;
@@ -191,10 +193,34 @@ static int batch_main(char** argv) {
   dyn.pattern = HD_PATTERN_Q;
   dyn.a = 2.0;
   dyn.b = 0.0;
-  if (!rc) rc = hd_batch_run(b, &dyn, px.data(), nullptr, ptx.data(), nullptr);
-  const int st = rc ? 0 : hd_batch_status(b);
-  write_file(argv[4], X, 4 * xout);
-  std::printf("rc %d status %d\n", rc, st);
+  if (!shapes) {
+    if (!rc)
+      rc = hd_batch_run(b, &dyn, px.data(), nullptr, ptx.data(), nullptr);
+    const int st = rc ? 0 : hd_batch_status(b);
+    write_file(argv[4], X, 4 * xout);
+    std::printf("rc %d status %d\n", rc, st);
+  } else {
+    // one run per shape digit, each after hd_batch_set_shape; 'a' runs the
+    // autotuner (one timed run per shape) and reports what it installed
+    int k = 0;
+    for (const char* c = shapes; *c && !rc; ++c) {
+      if (*c == 'a') {
+        int32_t ch = 0;
+        double ms[3];
+        rc = hd_batch_autotune(b, &dyn, px.data(), 1, ms, &ch);
+        std::printf("tuned %d shape %d\n", ch, hd_batch_shape(b));
+        continue;
+      }
+      rc = hd_batch_set_shape(b, *c - '0');
+      std::memset(X, 0, 4 * xout);
+      if (!rc)
+        rc = hd_batch_run(b, &dyn, px.data(), nullptr, ptx.data(), nullptr);
+      const int st = rc ? 0 : hd_batch_status(b);
+      write_file((std::string(argv[4]) + "." + std::to_string(k++)).c_str(),
+                 X, 4 * xout);
+      std::printf("shape %d rc %d status %d\n", hd_batch_shape(b), rc, st);
+    }
+  }
   hd_batch_free(b);
   std::free(x1);
   std::free(X);
@@ -202,7 +228,8 @@ static int batch_main(char** argv) {
 }
 
 int main(int argc, char** argv) {
-  if (argc == 5 && std::string(argv[1]) == "batch") return batch_main(argv);
+  if ((argc == 5 || argc == 6) && std::string(argv[1]) == "batch")
+    return batch_main(argv, argc == 6 ? argv[5] : nullptr);
   if ((argc == 14 || argc == 16) && std::string(argv[1]) == "ista")
     return ista_main(argv);
   if (argc == 12 && std::string(argv[1]) == "cplx") return cplx_main(argv);

@@ -247,3 +247,43 @@ def test_haar_batch_emulated(driver, tmp_path, cpt):
             worst = max(worst, np.abs(np.tanh(2 * orc.mv(Xi[t])) -
                                       Xi[t + 1]).max())
     assert worst < 1e-6
+
+
+def test_haar_batch_shapes_emulated(driver, tmp_path):
+    """The same batch switched between launch shapes in one process
+    (hd_batch_set_shape 1 -> 4 -> 2, then the autotuner, then 1 again): the
+    block map, partial-row counts and per-trial arguments follow each switch,
+    so every run's trajectory satisfies x_{t+1} = tanh(2 Q x_t) against the
+    oracle, and all runs agree to FP32 rounding."""
+    spec = [(1500, 6), (3000, 4), (700, 7)]
+    sf, xf, out = (str(tmp_path / f) for f in ("spec.bin", "x1.bin", "X.bin"))
+    np.array(spec, dtype=np.int64).ravel().tofile(sf)
+    np.concatenate([inputs.x1_normal(n, seed=0, trial=i).astype(np.float32)
+                    for i, (n, T) in enumerate(spec)]).tofile(xf)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("HD_BATCH_CPT", None)
+    r = subprocess.run([driver, "batch", sf, xf, out, "142a1"], env=env,
+                       capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    lines = r.stdout.strip().splitlines()
+    assert lines[:3] == ["shape 1 rc 0 status 0", "shape 4 rc 0 status 0",
+                         "shape 2 rc 0 status 0"], r.stdout
+    assert lines[3].startswith("tuned ")
+    assert lines[4] == "shape 1 rc 0 status 0", r.stdout
+    runs = [np.fromfile(out + ".%d" % k, dtype=np.float32).astype(np.float64)
+            for k in range(4)]
+    worst = 0.0
+    o = 0
+    for i, (n, T) in enumerate(spec):
+        orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=0, trial=i)
+        Xi = runs[0][o:o + n * (T + 1)].reshape(T + 1, n)
+        for t in range(T):
+            worst = max(worst, np.abs(np.tanh(2 * orc.mv(Xi[t])) -
+                                      Xi[t + 1]).max())
+        o += n * (T + 1)
+    assert worst < 1e-6
+    for k in range(1, 4):
+        assert np.abs(runs[k] - runs[0]).max() < 1e-5

@@ -169,3 +169,67 @@ def test_graph_replays_match_direct_runs():
             for a, b in zip(X + Y, Xd + Yd):
                 assert torch.equal(a, b), rep
         assert B.status() == 0 and D.status() == 0
+
+
+def test_shapes_and_autotuner():
+    """hd_batch_set_shape / hd_batch_autotune: one batch switched between
+    1, 2 and 4 chunks per workgroup (and back) answers every query as the
+    FP64 oracle does in each shape (Mode B, 1e-11), the shapes agree with
+    each other to FP64 rounding, and after the autotuner has timed all
+    three and installed one, runs still match the oracle.  With graph
+    replay on, a shape change drops the recorded graph: replays after it
+    equal direct runs of a second batch in the same shape bit for bit."""
+    B = hd.HaarBatch(TRIALS, dtype=torch.float64, device=DEV)
+    assert B.shape() == 4
+    x1 = _x1(torch.float64)
+
+    def run_and_check():
+        X, Y = B.run(x1, "tanh", 2.0, 0.0, record=True)
+        torch.cuda.synchronize()
+        assert B.status() == 0
+        worst = 0.0
+        for (n, T, s, k), Xi, Yi in zip(TRIALS, X, Y):
+            Xi = Xi.cpu().numpy()
+            orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=s, trial=k)
+            ref = oracle.replay(orc, Xi[:-1], [False] * T)
+            worst = max(worst, max(relerr(y, r) for y, r in
+                                   zip(Yi.cpu().numpy(), ref)))
+        assert worst < 1e-11, worst
+        return [y.cpu().numpy() for y in Y]
+
+    runs = {}
+    for c in (1, 2, 4, 1):
+        B.set_shape(c)
+        assert B.shape() == c
+        runs.setdefault(c, []).append(run_and_check())
+    for c in (2, 4):
+        for a, b in zip(runs[c][0], runs[1][0]):
+            assert relerr(a, b) < 1e-12
+    for a, b in zip(runs[1][0], runs[1][1]):
+        assert np.array_equal(a, b)
+    with pytest.raises(hd.HDError):
+        B.set_shape(3)
+    chosen, ms = B.autotune(x1, "tanh", 2.0, 0.0, reps=1)
+    print("batch autotuner: chose %d, ms per run %s" % (chosen, ms))
+    assert chosen in (1, 2, 4) and B.shape() == chosen
+    assert all(v > 0 for v in ms.values())
+    if chosen != 4:
+        assert ms[chosen] < 0.97 * ms[4]
+    run_and_check()
+    # graph replay across a shape change
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        G = hd.HaarBatch(TRIALS, dtype=torch.float32, device=DEV)
+        D = hd.HaarBatch(TRIALS, dtype=torch.float32, device=DEV)
+        G.set_graph(True)
+        xf = _x1(torch.float32)
+        for c in (4, 1, 2):
+            G.set_shape(c)
+            D.set_shape(c)
+            for _ in range(2):
+                got = [t.clone() for t in G.run(xf, "tanh", 2.0, 0.0)]
+                want = D.run(xf, "tanh", 2.0, 0.0)
+                s.synchronize()
+                for a, b in zip(got, want):
+                    assert torch.equal(a, b), c
+        assert G.status() == 0 and D.status() == 0
