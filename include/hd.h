@@ -277,8 +277,10 @@ int hd_lista_backward(hd_handle h, int32_t L, const float* a,
  * entries).  A handle created afterwards uses, per panel, the entry
  * whose length is nearest its own in ratio, if within a factor of 2, and
  * the built-in rule otherwise.  report: NULL or 3 * count doubles receiving
- * the mean microseconds per trajectory under 1, 2 and 4 chunks.  Not
- * thread-safe with concurrent hd_init.  The environment variable HD_CPT
+ * the mean microseconds per trajectory under 1, 2 and 4 chunks.  The
+ * tables are replaced atomically with respect to concurrent hd_init calls
+ * on other threads (each handle takes the shapes installed when it is
+ * created).  The environment variable HD_CPT
  * (1, 2 or 4), when set, overrides tuned and built-in shapes.
  * Errors: HD_ERR_INVALID (ensemble, storage, count < 1, k < 2, a length
  * below k or above 2^31), HD_ERR_NOMEM, HD_ERR_HIP. */

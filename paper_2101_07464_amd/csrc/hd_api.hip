@@ -125,10 +125,13 @@ int env_int(const char* name, int dflt) {
 // chunk below 256K rows, two below 512K, four from there on.  hd_autotune installs measured shapes per
 // ensemble and storage type: (panel length, cpt), sorted by length.  A
 // panel takes the entry whose length is nearest its own in ratio, if that
-// ratio is at most 2.  HD_CPT overrides both.
+// ratio is at most 2.  HD_CPT overrides both.  The tables are read by
+// hd_init and replaced by hd_autotune / hd_autotune_clear under g_tune_mu.
 std::vector<std::pair<int64_t, int>> g_tuned[2][2];
+std::mutex g_tune_mu;
 
 int tuned_cpt(int ens, int f64, int64_t dim) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
   int cpt = 0;
   double best = 2.0;
   for (const auto& e : g_tuned[ens == HD_HAAR ? 1 : 0][f64 ? 1 : 0]) {
@@ -149,9 +152,11 @@ Shape shape_of(int64_t ld, int cpt) {
   return sh;
 }
 
-// Set only inside hd_autotune: sizes its scratch handle for the one-chunk
-// shape (the most workgroups, hence the largest partial-sum buffers).
-int g_force_cpt = 0;
+// Set only inside hd_autotune, for its own thread: sizes its scratch
+// handle for the one-chunk shape (the most workgroups, hence the largest
+// partial-sum buffers); handles other threads create meanwhile are not
+// affected.
+thread_local int g_force_cpt = 0;
 
 // The built-in rule's chunks per workgroup for a panel of `dim` rows.
 int dim_rule(int64_t dim) {
@@ -1570,6 +1575,7 @@ int hd_autotune(int32_t ensemble, int32_t storage, const int64_t* lengths,
     table.push_back({n, best_cpt});
   }
   std::sort(table.begin(), table.end());
+  std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tuned[ensemble == HD_HAAR ? 1 : 0][f64] = table;
   return HD_OK;
 }
@@ -1584,6 +1590,7 @@ int hd_shape_rule(int32_t ensemble, int32_t storage, int64_t n, int32_t* cpt) {
 }
 
 int hd_autotune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
   for (auto& e : g_tuned)
     for (auto& t : e) t.clear();
   return HD_OK;
