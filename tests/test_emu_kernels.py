@@ -14,7 +14,8 @@ runs here through exactly the launches hd_run would issue for it (Haar,
 n = 4099, T = 30, FP32, the case of that fault): it must be clean under both
 sanitizers and agree with the FP64 oracle.  A Gaussian trajectory with Q and
 Q' alternating in the four-chunk launch shape covers the other ensemble and
-the row-split column dots, a small batch of unrolled-ISTA trials the
+the row-split column dots, the same in the one-chunk shape the workgroup
+prologues of both passes (z = T'w, the reflector step), a small batch of unrolled-ISTA trials the
 lockstep Gaussian batch and its reverse pass, and four ragged Haar trials the
 Haar batch in one and four chunks per workgroup.  The complex path
 (Sec. 3.4) runs mixed Q / Q^H
@@ -106,6 +107,22 @@ def test_gaussian_alternating_four_chunks_emulated(driver, tmp_path):
     Yb = oracle.replay(orc, X[:-1], [t % 2 == 1 for t in range(T)])
     eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
     print("emulated Gaussian, four chunks: mode B %.2e" % eb)
+    assert eb < 1e-4
+
+
+def test_gaussian_alternating_one_chunk_emulated(driver, tmp_path):
+    """One chunk per workgroup, where every workgroup of the data pass forms
+    z = T'w and every workgroup of the random pass the reflector step in
+    their prologues (the shape of the n = 65536 alternating workload).  Map
+    x_{t+1} = tanh(y_t) + 0.5 x_t."""
+    n, T, seed = 1100, 40, 3
+    x1 = inputs.x1_normal(n, seed=seed).astype(np.float32)
+    X, Y = _run(driver, tmp_path, 0, n, T, 1, 1.0, 0.5, 1, seed, 1, x1)
+    orc = oracle.HDOracle(oracle.GINIBRE, n, tmax=T, seed=seed,
+                          sigma=1.0 / np.sqrt(n))
+    Yb = oracle.replay(orc, X[:-1], [t % 2 == 1 for t in range(T)])
+    eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
+    print("emulated Gaussian, one chunk: mode B %.2e" % eb)
     assert eb < 1e-4
 
 
