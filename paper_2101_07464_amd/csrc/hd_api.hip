@@ -43,6 +43,8 @@ struct hd_ctx {
                    // kHintNone when no query is expected to follow
   double* partials;
   double* partials2;  // partial rows of the random-side pass
+  double* red_stage;  // two-stage reduction: one region per job (a, b)
+  size_t red_half;    // doubles per region
   ReduceJob deferred; // its sums, launched with the next reduction
   // The next query's TDOT dots, computed by the last random pass (its panel
   // is the next data side and its epilogue made the next input): valid for
@@ -325,6 +327,7 @@ int run_after(hd_ctx* h, int side, const After& af) {
   ja.nwg = h->sh[side].nwg;
   ja.rg = af.rg;
   ja.out = af.out;
+  ja.stage = h->red_stage;
   LCHK(launch_reduce(ja, h->deferred, h->stream));
   h->deferred = no_job();
   if (af.op == 1) LCHK(launch_small_data(af.sd, h->stream));
@@ -360,6 +363,7 @@ void defer_after(hd_ctx* h, int side, const After& af) {
   h->deferred.nwg = h->sh[side].nwg;
   h->deferred.rg = af.rg;
   h->deferred.out = af.out;
+  h->deferred.stage = h->red_stage + h->red_half;
 }
 
 // Which of this query's by-products the next one uses.  pf_data: the data
@@ -918,6 +922,8 @@ int init_layout(hd_ctx* h, const hd_config* cfg) {
   }
   ALLOC(h->partials, sizeof(double) * (size_t)maxwg * h->pstride);
   ALLOC(h->partials2, sizeof(double) * (size_t)maxwg * h->pstride);
+  h->red_half = red_stage_doubles(maxwg, h->pstride);
+  ALLOC(h->red_stage, sizeof(double) * 2 * h->red_half);
   h->hint = -1;
   h->deferred = no_job();
   ALLOC(h->w, sizeof(double) * h->pstride);

@@ -405,16 +405,31 @@ int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
 int launch_gin_pass(int f64, Shape sh, const GinPassArgs& a, hipStream_t s,
                     LaunchEvents ev = LaunchEvents());
 // Fixed-order sums of the partial rows of one pass: out[slot] = sum over
-// rows w < nwg of P[w * pstride + slot], for the slots in rg.
+// rows w < nwg of P[w * pstride + slot], for the slots in rg.  stage: room
+// for red_stage_doubles(nwg, pstride) doubles (the two-stage form's
+// per-block sums).
 struct ReduceJob {
   const double* P;
   int pstride;
   int nwg;
   SlotRanges rg;
   double* out;
+  double* stage;
 };
 
-// One launch for one or two jobs (job b may have no slots).
+// Partial rows per block of the two-stage reduction's first stage, and the
+// row count from which it is used (below it one block per slot reads the
+// rows directly; the environment variable HD_RED_TWO_STAGE overrides it).
+constexpr int kRed1Rows = 256;
+constexpr int kRedTwoStage = 1024;
+inline size_t red_stage_doubles(int nwg, int pstride) {
+  return (size_t)((nwg + kRed1Rows - 1) / kRed1Rows) * (size_t)pstride;
+}
+
+// The sums of one or two jobs (job b may have no slots): one launch when
+// both have at most kRedTwoStage rows, else two (blocks of kRed1Rows rows x
+// 32 consecutive slots, each row segment read as one contiguous run, then
+// the block sums per slot).
 int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s);
 int launch_small_data(const SmallDataArgs& a, hipStream_t s);
 int launch_haar_small(int f64, const HaarSmallArgs& a, hipStream_t s);

@@ -30,6 +30,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "hd_device.hpp"
 #include "hd_internal.hpp"
 
@@ -309,6 +311,46 @@ __device__ __forceinline__ void wg_sums(int nout, Lo lo, Hi hi, Term term,
   }
 }
 
+// out(j, s0_j, s1_j) for j < n with s_r,j = sum over l in [j, n) of
+// T[j, l] coef_r(l) (coef_1 only when NT = 2): the row sums of the leading
+// n x n block of an upper-triangular factor T (column-major, leading
+// dimension tm) against one or two coefficient vectors.  The lanes take the
+// rows and the waves the columns in turn, so every load reads consecutive
+// entries of one column (reading T by rows would touch one cache line per
+// entry); per block of 64 rows the waves' partial sums are added in fixed
+// order through LDS.  Every thread of the workgroup calls it; `lds` holds
+// 2 * kWG doubles.  Ends with a barrier.
+template <int NT, typename C0, typename C1, typename Out>
+__device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
+                                             int tm, int n, C0 coef0,
+                                             C1 coef1, Out out, double* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r0 = 0; r0 < n; r0 += 64) {
+    const int j = r0 + lane;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int l = r0 + wave; l < n; l += kWaves) {
+      if (j <= l) {
+        const double t = T[j + (int64_t)l * tm];
+        s0 += t * coef0(l);
+        if (NT == 2) s1 += t * coef1(l);
+      }
+    }
+    lds[tid] = s0;
+    if (NT == 2) lds[kWG + tid] = s1;
+    __syncthreads();
+    if (wave == 0 && j < n) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int w = 0; w < kWaves; ++w) {
+        a0 += lds[w * 64 + lane];
+        if (NT == 2) a1 += lds[kWG + w * 64 + lane];
+      }
+      out(j, a0, a1);
+    }
+    __syncthreads();
+  }
+}
+
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
 // Schreiber and Van Loan), then z = T' w for the leading k x k block.
 __device__ void small_data_body(const SmallDataArgs& a) {
@@ -319,12 +361,8 @@ __device__ void small_data_body(const SmallDataArgs& a) {
     const double tau = a.tau[kp];
     const double* c = a.c;
     double* Tw = a.T;
-    wg_sums<1>(
-        kp, [](int j) { return j; }, [kp](int) { return kp; },
-        [=](int l, int j, double& t0, double& t1) {
-          t0 = Tm[j + (int64_t)l * tm] * c[l];
-          t1 = 0.0;
-        },
+    tri_row_sums<1>(
+        Tm, tm, kp, [=](int l) { return c[l]; }, [](int) { return 0.0; },
         [=](int j, double r0, double) { Tw[j + (int64_t)kp * tm] = -tau * r0; },
         lds);
   }
@@ -381,13 +419,10 @@ __device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
   const double* __restrict__ Tm = D.T;
   double* Tw = D.T;
   const int64_t ld = D.ld;
-  wg_sums<1>(
-      k, [](int j) { return j; }, [k](int) { return k; },
-      [=](int l, int j, double& t0, double& t1) {
-        t0 = Tm[j + (int64_t)l * tm] *
-             (c[l] + (double)V[(int64_t)l * ld + k] * up);
-        t1 = 0.0;
-      },
+  tri_row_sums<1>(
+      Tm, tm, k,
+      [=](int l) { return c[l] + (double)V[(int64_t)l * ld + k] * up; },
+      [](int) { return 0.0; },
       [=](int j, double r0, double) { Tw[j + (int64_t)k * tm] = -tau * r0; },
       lds);
 }
@@ -459,13 +494,8 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
   const double* __restrict__ TG = a.G.T;
   double* TGw = a.G.T;
   double* zG = a.zG;
-  wg_sums<2>(
-      k, [](int j) { return j; }, [k](int) { return k; },
-      [=](int l, int j, double& t0, double& t1) {
-        const double tjl = TG[j + (int64_t)l * tm];
-        t0 = tjl * sv[l];
-        t1 = tjl * cG[l];
-      },
+  tri_row_sums<2>(
+      TG, tm, k, [=](int l) { return sv[l]; }, [=](int l) { return cG[l]; },
       [=](int j, double zz, double tg) {
         zG[j] = zz;
         TGw[j + (int64_t)k * tm] = -tauG * tg;
@@ -515,13 +545,8 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   const double* __restrict__ TG = a.G.T;
   double* z1 = a.z1;
   double* z2 = a.z2;
-  wg_sums<2>(
-      l, [](int j) { return j; }, [l](int) { return l; },
-      [=](int q, int j, double& t0, double& t1) {
-        const double tjq = TG[j + (int64_t)q * tm];
-        t0 = tjq * s1[q];
-        t1 = tjq * s2[q];
-      },
+  tri_row_sums<2>(
+      TG, tm, l, [=](int q) { return s1[q]; }, [=](int q) { return s2[q]; },
       [=](int j, double r0, double r1) {
         z1[j] = r0;
         z2[j] = r1;
@@ -708,12 +733,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
       const bool first = blk == 0;
       if (kp > 0) {
         const double tau = a.tau[kp];
-        wg_sums<1>(
-            kp, [](int j) { return j; }, [kp](int) { return kp; },
-            [=](int l, int j, double& t0, double& t1) {
-              t0 = Tm[j + (int64_t)l * tm] * cc[l];
-              t1 = 0.0;
-            },
+        tri_row_sums<1>(
+            Tm, tm, kp, [=](int l) { return cc[l]; }, [](int) { return 0.0; },
             [=](int j, double r0, double) {
               tc[j] = -tau * r0;
               if (first) Tw[j + (int64_t)kp * tm] = -tau * r0;
@@ -887,13 +908,9 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
           },
           comb);
       const double* __restrict__ TG = g.G.T;
-      wg_sums<2>(
-          l, [](int j) { return j; }, [l](int) { return l; },
-          [=](int q, int j, double& t0, double& t1) {
-            const double tjq = TG[j + (int64_t)q * tm];
-            t0 = tjq * s1l[q];
-            t1 = tjq * s2l[q];
-          },
+      tri_row_sums<2>(
+          TG, tm, l, [=](int q) { return s1l[q]; },
+          [=](int q) { return s2l[q]; },
           [=](int j, double r0, double r1) {
             z1l[j] = r0;
             z2l[j] = r1;
@@ -1387,6 +1404,71 @@ __global__ __launch_bounds__(kWG) void k_reduce(ReduceJob ja, ReduceJob jb) {
   if (threadIdx.x == 0) j.out[slot] = s;
 }
 
+// Two-stage form for many partial rows.  Stage 1: block (rb, pg) sums rows
+// [rb * kRed1Rows, (rb + 1) * kRed1Rows) of slot positions pg * 32 .. + 31
+// (positions count the slots of rg in order): thread (rl, sl) takes rows
+// rl, rl + 8, ... of position sl, so the 32 threads of a row read one
+// contiguous run of its slots; the 8 row lanes are added in order.
+constexpr int kRed1Pos = 32;
+constexpr int kRed1Lanes = kWG / kRed1Pos;
+
+__device__ __forceinline__ int red_positions(const ReduceJob& j) {
+  return j.rg.count[0] + j.rg.count[1] + j.rg.count[2];
+}
+__device__ __forceinline__ int red_blocks1(const ReduceJob& j) {
+  const int np = red_positions(j);
+  return np > 0 ? ((j.nwg + kRed1Rows - 1) / kRed1Rows) *
+                      ((np + kRed1Pos - 1) / kRed1Pos)
+                : 0;
+}
+
+__device__ __forceinline__ void reduce1_job(const ReduceJob& j, int b,
+                                            double* lds) {
+  const int np = red_positions(j);
+  const int npg = (np + kRed1Pos - 1) / kRed1Pos;
+  const int rb = b / npg, pg = b % npg;
+  const int tid = threadIdx.x, sl = tid % kRed1Pos, rl = tid / kRed1Pos;
+  const int p = pg * kRed1Pos + sl;
+  double s = 0.0;
+  if (p < np) {
+    const int slot = slot_of(j.rg, p);
+    const int r1 = min(j.nwg, (rb + 1) * kRed1Rows);
+    for (int r = rb * kRed1Rows + rl; r < r1; r += kRed1Lanes)
+      s += j.P[(int64_t)r * j.pstride + slot];
+  }
+  lds[tid] = s;
+  __syncthreads();
+  if (rl == 0 && p < np) {
+    double t = 0.0;
+    for (int q = 0; q < kRed1Lanes; ++q) t += lds[q * kRed1Pos + sl];
+    j.stage[(int64_t)rb * np + p] = t;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_reduce1(ReduceJob ja, ReduceJob jb) {
+  __shared__ double lds[kWG];
+  const int na = red_blocks1(ja);
+  if ((int)blockIdx.x < na)
+    reduce1_job(ja, blockIdx.x, lds);
+  else
+    reduce1_job(jb, blockIdx.x - na, lds);
+}
+
+// Stage 2: one thread per slot position, the block sums in row-block order.
+__global__ __launch_bounds__(kWG) void k_reduce2(ReduceJob ja, ReduceJob jb) {
+  const int g = blockIdx.x * kWG + threadIdx.x;
+  const int na = red_positions(ja);
+  const bool first = g < na;
+  const ReduceJob& j = first ? ja : jb;
+  const int p = first ? g : g - na;
+  const int np = red_positions(j);
+  if (p >= np) return;
+  const int nrb = (j.nwg + kRed1Rows - 1) / kRed1Rows;
+  double s = 0.0;
+  for (int rb = 0; rb < nrb; ++rb) s += j.stage[(int64_t)rb * np + p];
+  j.out[slot_of(j.rg, p)] = s;
+}
+
 __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
   small_data_body(a);
 }
@@ -1785,7 +1867,29 @@ int launch_reduce(const ReduceJob& a, const ReduceJob& b, hipStream_t s) {
   const int na = a.rg.count[0] + a.rg.count[1] + a.rg.count[2];
   const int nb = b.rg.count[0] + b.rg.count[1] + b.rg.count[2];
   if (na + nb <= 0) return 0;
-  hipLaunchKernelGGL(k_reduce, dim3(na + nb), dim3(kWG), 0, s, a, b);
+  // HD_RED_TWO_STAGE overrides the row count from which two stages are used
+  static const int from = [] {
+    const char* e = std::getenv("HD_RED_TWO_STAGE");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 1 ? v : kRedTwoStage;
+  }();
+  const bool two = (na > 0 && a.nwg > from) || (nb > 0 && b.nwg > from);
+  if (!two) {
+    hipLaunchKernelGGL(k_reduce, dim3(na + nb), dim3(kWG), 0, s, a, b);
+    HD_CHECK_LAUNCH();
+    return 0;
+  }
+  if ((na > 0 && !a.stage) || (nb > 0 && !b.stage)) return 1;
+  auto blocks1 = [](const ReduceJob& j, int np) {
+    return np > 0 ? ((j.nwg + kRed1Rows - 1) / kRed1Rows) *
+                        ((np + kRed1Pos - 1) / kRed1Pos)
+                  : 0;
+  };
+  hipLaunchKernelGGL(k_reduce1, dim3(blocks1(a, na) + blocks1(b, nb)),
+                     dim3(kWG), 0, s, a, b);
+  HD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_reduce2, dim3((na + nb + kWG - 1) / kWG), dim3(kWG), 0,
+                     s, a, b);
   HD_CHECK_LAUNCH();
   return 0;
 }

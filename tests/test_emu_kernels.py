@@ -56,12 +56,13 @@ def driver(tmp_path_factory):
     return out
 
 
-def _run(driver, tmp_path, ens, n, T, kind, a, b, pattern, seed, cpt, x1):
+def _run(driver, tmp_path, ens, n, T, kind, a, b, pattern, seed, cpt, x1,
+         extra_env=None):
     xf = str(tmp_path / "x1.bin")
     x1.astype(np.float32).tofile(xf)
     pre = str(tmp_path / "out")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-               UBSAN_OPTIONS="print_stacktrace=1")
+               UBSAN_OPTIONS="print_stacktrace=1", **(extra_env or {}))
     r = subprocess.run([driver, str(ens), str(n), str(T), str(kind), str(a),
                         str(b), str(pattern), str(seed), "0", "0", str(cpt),
                         xf, pre], env=env, capture_output=True, text=True,
@@ -123,6 +124,23 @@ def test_gaussian_alternating_one_chunk_emulated(driver, tmp_path):
     Yb = oracle.replay(orc, X[:-1], [t % 2 == 1 for t in range(T)])
     eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
     print("emulated Gaussian, one chunk: mode B %.2e" % eb)
+    assert eb < 1e-4
+
+
+def test_two_stage_reduction_emulated(driver, tmp_path):
+    """The two-stage reduction of the partial rows (blocks of 256 rows x 32
+    slots, then the block sums), which the library uses from 1024 rows per
+    pass on, here forced for every reduction (HD_RED_TWO_STAGE=1) on a Haar
+    trajectory with 264 one-chunk workgroups (two row blocks): Mode B
+    against the oracle."""
+    n, T = 66561, 4
+    x1 = inputs.x1_normal(n, seed=1).astype(np.float32)
+    X, Y = _run(driver, tmp_path, 1, n, T, 1, 1.0, 0.5, 0, 1, 1, x1,
+                extra_env={"HD_RED_TWO_STAGE": "1"})
+    orc = oracle.HDOracle(oracle.HAAR, n, tmax=T, seed=1)
+    Yb = oracle.replay(orc, X[:-1], [False] * T)
+    eb = max(relerr(y, yb) for y, yb in zip(Y, Yb))
+    print("emulated two-stage reduction: mode B %.2e" % eb)
     assert eb < 1e-4
 
 
