@@ -328,7 +328,8 @@ __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
   for (int r0 = 0; r0 < n; r0 += 64) {
     const int j = r0 + lane;
     double s0 = 0.0, s1 = 0.0;
-#pragma unroll 4
+    // unrolled so that many columns' loads are in flight at once
+#pragma unroll 16
     for (int l = r0 + wave; l < n; l += kWaves) {
       if (j <= l) {
         const double t = T[j + (int64_t)l * tm];
@@ -1433,6 +1434,7 @@ __device__ __forceinline__ void reduce1_job(const ReduceJob& j, int b,
   if (p < np) {
     const int slot = slot_of(j.rg, p);
     const int r1 = min(j.nwg, (rb + 1) * kRed1Rows);
+#pragma unroll 8
     for (int r = rb * kRed1Rows + rl; r < r1; r += kRed1Lanes)
       s += j.P[(int64_t)r * j.pstride + slot];
   }
@@ -1465,6 +1467,7 @@ __global__ __launch_bounds__(kWG) void k_reduce2(ReduceJob ja, ReduceJob jb) {
   if (p >= np) return;
   const int nrb = (j.nwg + kRed1Rows - 1) / kRed1Rows;
   double s = 0.0;
+#pragma unroll 8
   for (int rb = 0; rb < nrb; ++rb) s += j.stage[(int64_t)rb * np + p];
   j.out[slot_of(j.rg, p)] = s;
 }
