@@ -557,7 +557,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     a.z = h->zG;
     a.head = h->head;
     a.cscale = h->scal + 1;
-    a.y = y;
+    a.y = dyn.kind && dyn.y_unused ? nullptr : y;
     a.step = (uint32_t)step;
     a.want_ysq = want_ysq;
     a.dyn = dyn;
@@ -575,7 +575,7 @@ int haar_query(hd_ctx* h, int transpose, const void* x, void* y, int want_ysq,
     }
     {
       ProfScope ps(h, 2,
-                   es * ((double)h->ld[gs] * k + n + (n - k) +
+                   es * ((double)h->ld[gs] * k + (a.y ? n : 0) + (n - k) +
                          (dyn.kind ? 2.0 * n : 0.0)));
       LCHK(launch_pass(h->f64, h->sh[gs], kPassRandHaar, a, h->stream,
                        ps.ev));
@@ -685,7 +685,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     a.h = h->w + kD;
     a.scal = h->gscal;
     a.n = nG;
-    a.y = y;
+    a.y = dyn.kind && dyn.y_unused ? nullptr : y;
     a.key = Key{h->cfg.seed, h->cfg.trial};
     a.step = (uint32_t)step;
     a.dyn = dyn;
@@ -704,7 +704,7 @@ int gin_query(hd_ctx* h, int transpose, const void* x, void* y,
     }
     {
       ProfScope ps(h, 2,
-                   es * ((double)h->ld[gs] * (kG + kD) + 2.0 * nG +
+                   es * ((double)h->ld[gs] * (kG + kD) + (a.y ? 2.0 : 1.0) * nG +
                          (dyn.kind ? 2.0 * nG : 0.0)));
       LCHK(launch_gin_pass(h->f64, h->sh[gs], a, h->stream, ps.ev));
     }
@@ -1227,6 +1227,8 @@ static int run_dynamics(hd_handle h, const hd_dynamics* dyn, int32_t T,
       fz.xprev = xprev;
       fz.xnext = xrow(t + 1);
       fz.next_input = t < T;
+      // the internal buffer's answers are read by nobody
+      fz.y_unused = traj_y == nullptr;
     }
     int rc = query(h, transpose, xrow(t), y, dyn->kind == HD_DYN_NORMALIZE,
                    fz);

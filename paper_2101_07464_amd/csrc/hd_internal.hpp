@@ -119,6 +119,8 @@ struct DynFuse {
   void* aux;          // second output (kDynLista, kDynHead)
   int64_t len;        // kDynHead: rows kept; kDynScale: rows written
   int next_input;     // host only: xnext is the next query's input
+  int y_unused;       // host only: nothing reads the answer y afterwards, so
+                      // the pass that fuses the map does not store it
 };
 
 // Partial dots of panel columns with a right-hand side b (from memory, or the

@@ -796,7 +796,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
       } else {
         const double w = (i < k) ? a.head[i] : cs * gcur[q];
         const T ys = (T)(sg * w + vz[c]);
-        ((T*)a.y)[i] = ys;
+        if (a.y) ((T*)a.y)[i] = ys;
         ysq += (double)ys * (double)ys;
         double xn = 0.0;
         if (a.dyn.kind) xn = dyn_store<T>(a.dyn, i, (double)ys);
@@ -959,7 +959,7 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
       B[(int64_t)nb * a.ld + i] = (T)(sg * gi + u0[c]);
       const double hv = (i < k) ? a.h[i] : 0.0;
       const T ys = (T)(sigma * (u1[c] + sg * (hv + nu * gi)));
-      ((T*)a.y)[i] = ys;
+      if (a.y) ((T*)a.y)[i] = ys;
       if (a.dyn.kind) xn = dyn_store<T>(a.dyn, i, (double)ys);
     }
     gcur[q] = xn;  // this thread's own entry, already used

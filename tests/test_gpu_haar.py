@@ -136,3 +136,25 @@ def test_bitwise_reproducible():
         X, Y = A.run(x1, T, "tanh", 2.0, 0.0)
         outs.append(Y.cpu())
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("ens,n,T,dyn,a,b,pattern", [
+    (hd.HAAR, 100003, 12, "tanh", 1.0, 0.1, "Q"),      # one-chunk workgroups
+    (hd.HAAR, 600001, 6, "tanh", 1.0, 0.1, "Q"),       # four-chunk workgroups
+    (hd.GINIBRE, 70001, 12, "soft_hist", 0.1, 0.3, "alt"),
+])
+def test_unrecorded_run_equals_recorded(ens, n, T, dyn, a, b, pattern):
+    """hd_run without recorded answers (the fused map's pass then does not
+    store y, which nothing reads) reaches the same x_{T+1}, bit for bit, as
+    the same run recording every x_t and y_t."""
+    sig = 1.0 / np.sqrt(n) if ens == hd.GINIBRE else 1.0
+    x1 = torch.from_numpy(inputs.x1_normal(
+        n, seed=6, scale=1.0 if ens == hd.GINIBRE else None)).to(
+            DEV, torch.float32)
+    A = hd.LazyMatrix(ens, n, t_max=T, seed=6, sigma=sig, device=DEV)
+    X, _ = A.run(x1, T, dyn, a, b, pattern)
+    B = hd.LazyMatrix(ens, n, t_max=T, seed=6, sigma=sig, device=DEV)
+    xo, _ = B.run(x1, T, dyn, a, b, pattern, record=False)
+    torch.cuda.synchronize()
+    assert A.status() == 0 and B.status() == 0
+    assert torch.equal(xo, X[-1])
