@@ -243,10 +243,11 @@ def cpu_baseline(wl, budget_s=15.0):
 def batch_bytes(n, T, es=4):
     """Algorithmic bytes of one Haar trial, per query with k = t-1 reflectors
     per side: TDOT (k columns + x + the pending column), data pass (k columns
-    + x + the new column), random pass (k columns + y + the new column + x_t
-    read and x_{t+1} written by the fused map)."""
+    + x + the new column), random pass (k columns + the new column + x_t
+    read and x_{t+1} written by the fused map; y itself is not stored when
+    the run does not record it)."""
     k = np.arange(T, dtype=np.float64)
-    return float(es * np.sum(3.0 * n * k + 8.0 * n))
+    return float(es * np.sum(3.0 * n * k + 7.0 * n))
 
 
 def run_batch(args, steps, warmup):

@@ -37,7 +37,7 @@ struct hd_batch_ctx {
   int* blk_first_d = nullptr;
   CopyJob* jobs = nullptr;         // 2 * count entries
   char* arena = nullptr;
-  std::vector<size_t> ring_off;    // per run position: x ring (3 n), y (n)
+  std::vector<size_t> ring_off;    // per run position: x ring (3 n)
   int* flag = nullptr;
   void* zeros = nullptr;
   std::vector<void*> allocs;
@@ -117,7 +117,7 @@ int balloc(hd_batch_ctx* b, P** out, size_t bytes) {
 // Offsets of one trial's buffers inside the arena.
 struct Layout {
   size_t V[2], T[2], tau[2], nu[2], piv[2], sgn[2], pi[2], red[2];
-  size_t part, part2, w, zD, zG, head, scal, ring, y;
+  size_t part, part2, w, zD, zG, head, scal, ring;
   size_t end;
 };
 
@@ -149,7 +149,6 @@ Layout layout_of(size_t base, int64_t n, int T, int es, int nwg,
   L.head = take(sizeof(double) * T);
   L.scal = take(sizeof(double) * 8);
   L.ring = take((size_t)es * 3 * n);
-  L.y = take((size_t)es * n);
   L.end = o;
   return L;
 }
@@ -427,7 +426,7 @@ int hd_batch_run(hd_batch b, const hd_dynamics* dyn, const void* const* x1,
     char* ring = b->arena + b->ring_off[i];
     d.xbase = traj_x ? traj_x[c] : ring;
     d.xmod = traj_x ? t.T + 1 : 3;
-    d.ybase = traj_y ? traj_y[c] : ring + (size_t)b->es * 3 * t.n;
+    d.ybase = traj_y ? traj_y[c] : nullptr;  // unrecorded answers: not stored
     d.ymod = traj_y ? t.T : 1;
     d.pr.dyn.kind = dyn->kind;
     d.pr.dyn.a = dyn->a;

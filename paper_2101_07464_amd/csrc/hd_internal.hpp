@@ -329,7 +329,6 @@ struct IstaTrialDev {
   void* res;   // m: y - Q x_t (reverse pass: Q gbar)
   void* U;     // n: Q'(y - Q x_t) (query output)
   void* V;     // n: x_t + a_t Q'(y - Q x_t)
-  void* Yq;    // m: Q x_t (query output)
   void* gbar;  // n: reverse pass, g masked by the threshold (or null)
 };
 

@@ -107,7 +107,7 @@ int ialloc(hd_ista_ctx* b, P** out, size_t bytes) {
 // Offsets of one trial's buffers inside its block of the arena.
 struct Lay {
   size_t V[2], B[2], T[2], tau[2], nu[2], piv[2], sgn[2], pi[2], red[2];
-  size_t part, w, zD, zG, z2, head, scal, gscal, yobs, res, U, V2, Yq, gbar;
+  size_t part, w, zD, zG, z2, head, scal, gscal, yobs, res, U, V2, gbar;
   size_t end;
 };
 
@@ -154,7 +154,6 @@ Lay layout(const int64_t* ld, int L, int grad, int es, int pstride,
   y.gscal = take(sizeof(double) * 8);
   y.yobs = take((size_t)es * m);
   y.res = take((size_t)es * m);
-  y.Yq = take((size_t)es * m);
   y.U = take((size_t)es * n);
   y.V2 = take((size_t)es * n);
   y.gbar = grad ? take((size_t)es * n) : 0;
@@ -352,7 +351,6 @@ int hd_ista_init(int32_t storage, int64_t m, int64_t n, int32_t L,
     }
     d.yobs = A + lay.yobs;
     d.res = A + lay.res;
-    d.Yq = A + lay.Yq;
     d.U = A + lay.U;
     d.V = A + lay.V2;
     d.gbar = grad ? A + lay.gbar : nullptr;

@@ -1077,7 +1077,9 @@ __global__ __launch_bounds__(kWG) void k_pass_batch(const TrialDev* D,
   if (MODE == kPassData) {
     a.x = batch_vec<T>(d.xbase, d.xmod, n, t);
   } else {
-    a.y = (void*)batch_vec<T>(d.ybase, d.ymod, n, t);
+    // y is stored only when the run records it (the map reads it from
+    // registers)
+    a.y = d.ybase ? (void*)batch_vec<T>(d.ybase, d.ymod, n, t) : nullptr;
     a.pf = (int)st.step < d.T;
     a.pf_step = st.step + 1;
     a.pf_cut = st.k + 1;
@@ -1245,8 +1247,8 @@ __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
   a.dyn.xprev = nullptr;
   a.dyn.aux = nullptr;
   if (st.q == 0) {
-    // y = sigma Q x* + w
-    a.y = d.Yq;
+    // y = sigma Q x* + w (Q x* itself is not kept)
+    a.y = nullptr;
     a.dyn.kind = kDynAxpy;
     a.dyn.a = -1.0;
     a.dyn.b = 1.0;
@@ -1266,8 +1268,8 @@ __global__ __launch_bounds__(kWG) void k_ista_rand(const IstaTrialDev* D,
     a.dyn.x = d.gbar;
     a.dyn.xnext = (T*)st.G + (int64_t)trial * n;
   } else if (gs == 1) {
-    // Q x_t, then y - Q x_t
-    a.y = d.Yq;
+    // Q x_t, then y - Q x_t (only the residual is kept)
+    a.y = nullptr;
     a.dyn.kind = kDynResidual;
     a.dyn.x = d.yobs;
     a.dyn.xnext = d.res;
