@@ -185,23 +185,39 @@ __device__ __forceinline__ void cdots(const T* __restrict__ P, int64_t ld,
                                       const cd (&b0)[kRPT],
                                       const cd (&b1)[kRPT], int nc1,
                                       double* out0, double* out1) {
-  // four complex columns per group (two with two right-hand sides): 104
-  // VGPRs and four waves per SIMD in complex64, 3% faster than eight at 140
   constexpr int CG = 4 / NR;
   constexpr int NV = 2 * CG * NR;
   constexpr int kStep = 64 / NV;
+  using V2 = typename Vec2<T>::V;
   const int lane = threadIdx.x & 63;
+  // four complex columns per group (two with two right-hand sides); the raw
+  // entries of the next group are loaded before the current group's
+  // products and reduction, so two groups of loads are in flight (138 VGPRs,
+  // three waves per SIMD in complex64: 2% faster than one group at 104 VGPRs
+  // and four waves)
+  V2 cur[CG][kRPT], nxt[CG][kRPT];
+  auto load = [&](int j0, V2 (&buf)[CG][kRPT]) {
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      const int j = min(j0 + c, nc - 1);
+      const T* __restrict__ col = P + 2 * (int64_t)j * ld;
+#pragma unroll
+      for (int e = 0; e < kRPT; ++e)
+        buf[c][e] = *(const V2*)(col + 2 * row[e]);
+    }
+  };
+  if (nc > 0) load(0, cur);
   for (int j0 = 0; j0 < nc; j0 += CG) {
+    if (j0 + CG < nc) load(j0 + CG, nxt);
     double v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.0;
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
       if (j0 + c < nc) {
-        const T* __restrict__ col = P + 2 * (int64_t)(j0 + c) * ld;
 #pragma unroll
         for (int e = 0; e < kRPT; ++e) {
-          const cd u = ldc<T>(col, row[e]);
+          const cd u{(double)cur[c][e].x, (double)cur[c][e].y};
           v[2 * c] += u.re * b0[e].re + u.im * b0[e].im;
           v[2 * c + 1] += u.re * b0[e].im - u.im * b0[e].re;
           if (NR == 2) {
@@ -220,6 +236,12 @@ __device__ __forceinline__ void cdots(const T* __restrict__ P, int64_t ld,
         const int q1 = q - 2 * CG;
         if (j0 + q1 / 2 < nc1) out1[2 * j0 + q1] = r;
       }
+    }
+    if (j0 + CG < nc) {
+#pragma unroll
+      for (int c = 0; c < CG; ++c)
+#pragma unroll
+        for (int e = 0; e < kRPT; ++e) cur[c][e] = nxt[c][e];
     }
   }
 }
