@@ -125,7 +125,7 @@ __device__ __forceinline__ void combine_rows(const double (&acc)[CPT][4],
 // workgroup's rows); rows at or beyond n are zero.  NT: non-temporal panel
 // loads (used for multi-chunk workgroups -- panels far beyond the caches --
 // when no second sweep re-reads the rows).
-template <typename T, int CPT, int ND, int NZ, bool NT = false>
+template <typename T, int CPT, int ND, int NZ, bool NT = false, bool DB = false>
 __device__ __forceinline__ void sweep(
     const T* __restrict__ V, int64_t ld, int nc, int64_t blk0,
     const double (&rhs0)[CPT][4], const double (&rhs1)[CPT][4], bool dots,
@@ -137,6 +137,74 @@ __device__ __forceinline__ void sweep(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ncw = nc > wave ? (nc - wave + kWaves - 1) / kWaves : 0;
   const T* __restrict__ Vl = V + blk0 + 4 * lane;
+  if constexpr (DB && sizeof(T) == 4) {
+    // DB: the raw entries of the next column group are loaded before the
+    // current group's arithmetic, so two groups of loads are in flight (for
+    // workgroups alone on their CU, where nothing else hides the latency)
+    hd_f4 cur[CPT][kCG], nxt[CPT][kCG];
+    auto load = [&](int g0, hd_f4 (&buf)[CPT][kCG]) {
+#pragma unroll
+      for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int jj = 0; jj < kCG; ++jj) {
+          const int j = wave + kWaves * min(g0 + jj, ncw - 1);
+          const hd_f4* p = (const hd_f4*)(Vl + (int64_t)j * ld + c * kChunkRows);
+          if constexpr (NT)
+            buf[c][jj] = __builtin_nontemporal_load(p);
+          else
+            buf[c][jj] = *p;
+        }
+    };
+    if (ncw > 0) load(0, cur);
+#pragma unroll 1
+    for (int g0 = 0; g0 < ncw; g0 += kCG) {
+      if (g0 + kCG < ncw) load(g0 + kCG, nxt);
+      double p0[kCG], p1[ND == 2 ? kCG : 1];
+      double q0[NZ >= 1 ? kCG : 1], q1[NZ == 2 ? kCG : 1];
+#pragma unroll
+      for (int jj = 0; jj < kCG; ++jj) {
+        const bool ok = g0 + jj < ncw;
+        const int j = wave + kWaves * (g0 + jj);
+        p0[jj] = 0.0;
+        if constexpr (ND == 2) p1[jj] = 0.0;
+        if constexpr (NZ >= 1) q0[jj] = ok ? zs0 * z0[j] : 0.0;
+        if constexpr (NZ == 2) q1[jj] = ok ? zs1 * z1[j] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+        for (int jj = 0; jj < kCG; ++jj) {
+          double v[4] = {cur[c][jj].x, cur[c][jj].y, cur[c][jj].z, cur[c][jj].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if constexpr (NZ >= 1) acc0[c][e] -= v[e] * q0[jj];
+            if constexpr (NZ == 2) acc1[c][e] -= v[e] * q1[jj];
+            if constexpr (ND >= 1) p0[jj] += v[e] * rhs0[c][e];
+            if constexpr (ND == 2) p1[jj] += v[e] * rhs1[c][e];
+          }
+        }
+      }
+      if constexpr (ND >= 1) {
+        if (dots) {
+          const int q = g0 + lane / kGroup;
+          const bool owner = (lane % kGroup) == 0 && q < ncw;
+          const double s0 = wave_reduce_scatter<kCG>(p0);
+          if (owner) out0[wave + kWaves * q] = s0;
+          if constexpr (ND == 2) {
+            const double s1 = wave_reduce_scatter<kCG>(p1);
+            if (owner) out1[wave + kWaves * q] = s1;
+          }
+        }
+      }
+      if (g0 + kCG < ncw) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+          for (int jj = 0; jj < kCG; ++jj) cur[c][jj] = nxt[c][jj];
+      }
+    }
+    return;
+  }
 #pragma unroll 1
   for (int g0 = 0; g0 < ncw; g0 += kCG) {
     double p0[kCG], p1[ND == 2 ? kCG : 1];
@@ -638,7 +706,7 @@ __device__ __forceinline__ void tdot_rs(const TdotArgs& a, int blk) {
   }
 }
 
-template <typename T, int CPT, bool GEN, bool TWO>
+template <typename T, int CPT, bool GEN, bool TWO, bool DB = false>
 __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
   if constexpr (CPT == 4) {
     tdot_rs<T, GEN, TWO>(a, blk);
@@ -669,11 +737,13 @@ __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
   double* out = a.partials + (int64_t)blk * a.pstride;
   double acc[CPT][4];
   constexpr bool kNT = CPT > 1;
-  sweep<T, CPT, TWO ? 2 : 1, 0, kNT>((const T*)a.V, a.ld, a.ncols, blk0, rhs0,
+  sweep<T, CPT, TWO ? 2 : 1, 0, kNT, DB>((const T*)a.V, a.ld, a.ncols, blk0,
+                                         rhs0,
                                      rhs1, true, nullptr, 0.0, nullptr, 0.0,
                                      acc, acc, out, out + a.slot2);
   if (a.ncols2 > 0)
-    sweep<T, CPT, 1, 0, kNT>((const T*)a.V2, a.ld, a.ncols2, blk0, rhs0, rhs1,
+    sweep<T, CPT, 1, 0, kNT, DB>((const T*)a.V2, a.ld, a.ncols2, blk0, rhs0,
+                                 rhs1,
                              true, nullptr, 0.0, nullptr, 0.0, acc, acc,
                              out + a.ncols, nullptr);
   if (a.want_ss) {
@@ -696,7 +766,7 @@ __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
 
 // ---------------------------------------------------------------- GEMV-N --
 
-template <typename T, int CPT, int MODE>
+template <typename T, int CPT, int MODE, bool DB = false>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
   __shared__ double gpf[CPT * kChunkRows];   // next draw (prefetch)
   __shared__ double gcur[CPT * kChunkRows];  // this draw, or the new column
@@ -758,10 +828,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
   const bool reread = (MODE == kPassData && a.cslot >= 0) ||
                       (MODE == kPassRandHaar && a.wnext);
   if (CPT > 1 && !reread)
-    sweep<T, CPT, 1, 1, true>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0,
+    sweep<T, CPT, 1, 1, true, DB>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0,
                               nullptr, 0.0, acc, acc, out, nullptr);
   else
-    sweep<T, CPT, 1, 1>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0, nullptr,
+    sweep<T, CPT, 1, 1, false, DB>(V, a.ld, k, blk0, gn, gn, a.pf != 0, z, 1.0,
+                                   nullptr,
                         0.0, acc, acc, out, nullptr);
   double vz[CPT];  // -(V z) for this thread's rows
   combine_rows<CPT>(acc, comb, vz);
@@ -816,7 +887,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     __syncthreads();
     double xr[CPT][4];
     lane_rows<CPT>(gcur, xr);
-    sweep<T, CPT, 1, 0>(V, a.ld, k + 1, blk0, xr, xr, true, nullptr, 0.0,
+    sweep<T, CPT, 1, 0, false, DB>(V, a.ld, k + 1, blk0, xr, xr, true, nullptr,
+                                   0.0,
                         nullptr, 0.0, acc, acc, out, nullptr);
   }
   if (MODE == kPassData && a.cslot >= 0) {
@@ -825,7 +897,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
     __syncthreads();
     double ur[CPT][4];
     lane_rows<CPT>(gcur, ur);
-    sweep<T, CPT, 1, 0>(V, a.ld, k, blk0, ur, ur, true, nullptr, 0.0, nullptr,
+    sweep<T, CPT, 1, 0, false, DB>(V, a.ld, k, blk0, ur, ur, true, nullptr, 0.0,
+                                   nullptr,
                         0.0, acc, acc, out + a.cslot, nullptr);
   }
   if (MODE == kPassData) {
@@ -847,7 +920,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
 
 // ------------------------------------------------- Ginibre random side --
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool DB = false>
 __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   __shared__ double gpf[CPT * kChunkRows];
   __shared__ double gcur[CPT * kChunkRows];
@@ -926,20 +999,22 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
   // and the prefetch dots
   if (CPT > 1 && !a.wnext) {
-    sweep<T, CPT, 1, 2, true>((const T*)a.V, a.ld, k, blk0, gn, gn,
+    sweep<T, CPT, 1, 2, true, DB>((const T*)a.V, a.ld, k, blk0, gn, gn,
                               a.pf != 0, z1, 1.0, z2, 1.0, acc0, acc1, out,
                               nullptr);
     // explicit basis panel: acc1 += B c
     if (nb > 0)
-      sweep<T, CPT, 0, 1, true>((const T*)B, a.ld, nb, blk0, gn, gn, false,
+      sweep<T, CPT, 0, 1, true, DB>((const T*)B, a.ld, nb, blk0, gn, gn, false,
                                 a.c, -1.0, nullptr, 0.0, acc1, acc1, nullptr,
                                 nullptr);
   } else {
-    sweep<T, CPT, 1, 2>((const T*)a.V, a.ld, k, blk0, gn, gn, a.pf != 0, z1,
+    sweep<T, CPT, 1, 2, false, DB>((const T*)a.V, a.ld, k, blk0, gn, gn,
+                                   a.pf != 0, z1,
                         1.0, z2, 1.0, acc0, acc1, out, nullptr);
     // explicit basis panel: acc1 += B c
     if (nb > 0)
-      sweep<T, CPT, 0, 1>((const T*)B, a.ld, nb, blk0, gn, gn, false, a.c,
+      sweep<T, CPT, 0, 1, false, DB>((const T*)B, a.ld, nb, blk0, gn, gn, false,
+                                     a.c,
                           -1.0, nullptr, 0.0, acc1, acc1, nullptr, nullptr);
   }
   double u0[CPT], u1[CPT];
@@ -971,28 +1046,30 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
     __syncthreads();
     double xr[CPT][4];
     lane_rows<CPT>(gcur, xr);
-    sweep<T, CPT, 1, 0>((const T*)a.V, a.ld, k, blk0, xr, xr, true, nullptr,
+    sweep<T, CPT, 1, 0, false, DB>((const T*)a.V, a.ld, k, blk0, xr, xr, true,
+                                   nullptr,
                         0.0, nullptr, 0.0, acc0, acc0, out, nullptr);
-    sweep<T, CPT, 1, 0>((const T*)B, a.ld, nb + 1, blk0, xr, xr, true, nullptr,
+    sweep<T, CPT, 1, 0, false, DB>((const T*)B, a.ld, nb + 1, blk0, xr, xr,
+                                   true, nullptr,
                         0.0, nullptr, 0.0, acc0, acc0, out + k, nullptr);
   }
 }
 
 // ---------------------------------------------------- kernel wrappers ----
 
-template <typename T, int CPT, bool GEN, bool TWO>
+template <typename T, int CPT, bool GEN, bool TWO, bool DB = false>
 __global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
-  tdot_body<T, CPT, GEN, TWO>(a, blockIdx.x);
+  tdot_body<T, CPT, GEN, TWO, DB>(a, blockIdx.x);
 }
 
-template <typename T, int CPT, int MODE>
+template <typename T, int CPT, int MODE, bool DB = false>
 __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
-  pass_body<T, CPT, MODE>(a, blockIdx.x);
+  pass_body<T, CPT, MODE, DB>(a, blockIdx.x);
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool DB = false>
 __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
-  gin_pass_body<T, CPT>(a, blockIdx.x);
+  gin_pass_body<T, CPT, DB>(a, blockIdx.x);
 }
 
 // --------------------------------------------------- ISTA layer adjoint --
@@ -1576,9 +1653,23 @@ static void panel_launch(void (*k)(KArgs...), int nwg, hipStream_t s,
       return -1;                                                  \
   } while (0)
 
+// One-chunk FP32 launches of at most one workgroup per CU take the sweeps
+// with two column groups in flight (DB): nothing else on the CU hides their
+// load latency.  Wider launches keep the lighter single-group form.
+constexpr int kDbMaxWG = 256;
+template <typename T>
+bool use_db(Shape sh) {
+  return sizeof(T) == 4 && sh.cpt == 1 && sh.nwg <= kDbMaxWG;
+}
+
 template <typename T, bool GEN, bool TWO>
 static int tdot_shape(Shape sh, const TdotArgs& a, hipStream_t s,
                       LaunchEvents ev) {
+  if (use_db<T>(sh)) {
+    panel_launch(k_tdot<T, 1, GEN, TWO, true>, sh.nwg, s, ev, a);
+    HD_CHECK_LAUNCH();
+    return 0;
+  }
 #define K_(C) k_tdot<T, C, GEN, TWO>
   HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
@@ -1602,6 +1693,11 @@ int launch_tdot(int f64, Shape sh, const TdotArgs& a, hipStream_t s,
 template <typename T, int MODE>
 static int pass_shape(Shape sh, const PassArgs& a, hipStream_t s,
                       LaunchEvents ev) {
+  if (use_db<T>(sh)) {
+    panel_launch(k_pass<T, 1, MODE, true>, sh.nwg, s, ev, a);
+    HD_CHECK_LAUNCH();
+    return 0;
+  }
 #define K_(C) k_pass<T, C, MODE>
   HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
@@ -1621,6 +1717,11 @@ int launch_pass(int f64, Shape sh, int mode, const PassArgs& a,
 template <typename T>
 static int gin_shape(Shape sh, const GinPassArgs& a, hipStream_t s,
                      LaunchEvents ev) {
+  if (use_db<T>(sh)) {
+    panel_launch(k_gin_pass<T, 1, true>, sh.nwg, s, ev, a);
+    HD_CHECK_LAUNCH();
+    return 0;
+  }
 #define K_(C) k_gin_pass<T, C>
   HD_DISPATCH_EV(sh, K_, s, ev, a);
 #undef K_
