@@ -1653,10 +1653,11 @@ static void panel_launch(void (*k)(KArgs...), int nwg, hipStream_t s,
       return -1;                                                  \
   } while (0)
 
-// One-chunk FP32 launches of at most one workgroup per CU take the sweeps
-// with two column groups in flight (DB): nothing else on the CU hides their
-// load latency.  Wider launches keep the lighter single-group form.
-constexpr int kDbMaxWG = 256;
+// One-chunk FP32 launches of up to four workgroups per CU (the panels below
+// 256K rows) take the sweeps with two column groups in flight (DB): few
+// waves per CU are left to hide their load latency.  Wider launches keep
+// the lighter single-group form.
+constexpr int kDbMaxWG = 1024;
 template <typename T>
 bool use_db(Shape sh) {
   return sizeof(T) == 4 && sh.cpt == 1 && sh.nwg <= kDbMaxWG;
