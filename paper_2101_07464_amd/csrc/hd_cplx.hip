@@ -757,15 +757,63 @@ __device__ void build_reflector(const SideDev& S, int f64, int k, double ss,
   st2(S.del + 2 * k, cmul(prev, c));
 }
 
+// out(j, s_j) for j < n with s_j = sum over i in [j, n) of T[j, i] v(i):
+// the row sums of the leading n x n block of a side's complex T factor
+// (column-major, leading dimension kmax).  The lanes take the rows and the
+// waves the columns in turn, so every load reads consecutive entries of one
+// column (a thread summing its own row would touch one cache line per
+// entry, in a serial chain); per block of 64 rows the waves' partial sums
+// are added in fixed order through `lds` (kWG entries).  Every thread of
+// the workgroup calls it; it ends with a barrier.
+template <typename V, typename Out>
+__device__ void t_row_sums(const double* __restrict__ T, int kmax, int n,
+                           V v, Out out, cd* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r0 = 0; r0 < n; r0 += 64) {
+    const int j = r0 + lane;
+    cd s{0.0, 0.0};
+#pragma unroll 8
+    for (int i = r0 + wave; i < n; i += kWaves)
+      if (j <= i) s = cadd(s, cmul(ld2(tij((double*)T, kmax, j, i)), v(i)));
+    lds[tid] = s;
+    __syncthreads();
+    if (wave == 0 && j < n) {
+      cd t{0.0, 0.0};
+      for (int w = 0; w < kWaves; ++w) t = cadd(t, lds[w * 64 + lane]);
+      out(j, t);
+    }
+    __syncthreads();
+  }
+}
+
+// out(j, s_j) for j < nc with s_j = sum over i in [lo(j), hi(j)) of
+// f(i, j), where f reads column j of a column-major factor (a panel or T):
+// the waves take the columns in turn and the lanes the rows, so each load
+// reads consecutive entries of one column, and a butterfly over the wave
+// adds the lanes' terms.  Every thread of the workgroup calls it; no
+// barrier.
+template <typename Lo, typename Hi, typename F, typename Out>
+__device__ void col_dots(int nc, Lo lo, Hi hi, F f, Out out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < nc; j += kWaves) {
+    cd s{0.0, 0.0};
+    const int e = hi(j);
+    for (int i = lo(j) + lane; i < e; i += 64) s = cadd(s, f(i, j));
+    s.re = wave_sum(s.re);
+    s.im = wave_sum(s.im);
+    if (lane == 0) out(j, s);
+  }
+}
+
 // T column k of a side: T[j, k] = -tau sum_{i = j}^{k-1} T[j, i] h_i,
 // T[k, k] = tau, with h (LDS) the dots of the old columns with the new one.
-__device__ void t_column(const SideDev& S, int kmax, int k, const cd* h) {
+__device__ void t_column(const SideDev& S, int kmax, int k, const cd* h,
+                         cd* lds) {
   const double tau = S.ref[(int64_t)k * kRefStride + kRefTau];
-  for (int j = threadIdx.x; j < k; j += kWG) {
-    cd s{0.0, 0.0};
-    for (int i = j; i < k; ++i) s = cadd(s, cmul(ld2(tij(S.T, kmax, j, i)), h[i]));
-    st2(tij(S.T, kmax, j, k), cscale(-tau, s));
-  }
+  double* T = S.T;
+  t_row_sums(
+      T, kmax, k, [=](int i) { return h[i]; },
+      [=](int j, cd s) { st2(tij(T, kmax, j, k), cscale(-tau, s)); }, lds);
   if (threadIdx.x == 0) st2(tij(S.T, kmax, k, k), {tau, 0.0});
 }
 
@@ -777,6 +825,7 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
   __shared__ cd h[kSmallMax];
   __shared__ cd h2[kSmallMax];
   __shared__ cd piv[2];
+  __shared__ cd lds[kWG];
   const int tid = threadIdx.x, kmax = a.kmax;
   if (PH == 0) {
     if (a.pk >= 0) {
@@ -787,16 +836,17 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
       for (int j = tid; j < pk; j += kWG)
         h[j] = cadd(ld2(a.red + a.rl.t + 2 * j), cjmul(uent(a.P, a.f64, pk, j), up));
       __syncthreads();
-      t_column(a.P, kmax, pk, h);
+      t_column(a.P, kmax, pk, h, lds);
       __syncthreads();
     }
-    const int k = a.kD;
-    for (int j = tid; j < k; j += kWG) {
-      cd z{0.0, 0.0};
-      for (int i = 0; i <= j; ++i)
-        z = cadd(z, cjmul(ld2(tij(a.D.T, kmax, i, j)), ld2(a.red + a.rl.w + 2 * i)));
-      st2(a.coef + a.cl.z + 2 * j, z);
-    }
+    // z_j = sum over i <= j of conj(T_D[i, j]) w_i
+    double* T = a.D.T;
+    const double* w = a.red + a.rl.w;
+    double* z = a.coef + a.cl.z;
+    col_dots(
+        a.kD, [](int) { return 0; }, [](int j) { return j + 1; },
+        [=](int i, int j) { return cjmul(ld2(tij(T, kmax, i, j)), ld2(w + 2 * i)); },
+        [=](int j, cd v) { st2(z + 2 * j, v); });
     return;
   }
   const int kD = a.kD;
@@ -820,7 +870,7 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
     for (int j = tid; j < kD; j += kWG)
       h2[j] = cadd(ld2(a.red + a.rl.e + 2 * j), cjmul(uent(a.G, a.f64, kD, j), piv[1]));
     __syncthreads();
-    t_column(a.G, kmax, kD, h2);
+    t_column(a.G, kmax, kD, h2, lds);
     __syncthreads();
   }
   if (PH == 1) {
@@ -835,18 +885,22 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
       st2(a.coef + a.cl.s + 2 * i, s);
     }
     __syncthreads();
-    for (int j = tid; j <= k; j += kWG) {
-      cd s{0.0, 0.0};
-      for (int i = j; i < k; ++i) s = cadd(s, cjmul(uent(a.G, a.f64, i, j), h[i]));
-      const cd ukj = j < k ? uent(a.G, a.f64, k, j) : piv[1];
-      h2[j] = cadd(s, cjmul(ukj, h[k]));
-    }
+    // h2_j = sum over i in [j, k] of conj(U_G[i, j]) s_i (the new pivot
+    // entry in FP64)
+    const SideDev G = a.G;
+    const int f64 = a.f64;
+    const cd pk = piv[1];
+    col_dots(
+        k + 1, [](int j) { return j; }, [=](int) { return k + 1; },
+        [=](int i, int j) {
+          return cjmul(i == k && j == k ? pk : uent(G, f64, i, j), h[i]);
+        },
+        [=](int j, cd v) { h2[j] = v; });
     __syncthreads();
-    for (int j = tid; j <= k; j += kWG) {
-      cd c{0.0, 0.0};
-      for (int i = j; i <= k; ++i) c = cadd(c, cmul(ld2(tij(a.G.T, kmax, j, i)), h2[i]));
-      st2(a.coef + a.cl.c1 + 2 * j, c);
-    }
+    double* coef = a.coef + a.cl.c1;
+    t_row_sums(
+        a.G.T, kmax, k + 1, [=](int i) { return h2[i]; },
+        [=](int j, cd c) { st2(coef + 2 * j, c); }, lds);
     return;
   }
   // PH 2 (Ginibre): G has kG reflectors and gets none
@@ -866,22 +920,26 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
   }
   __syncthreads();
   // c' = T_G e'; U_G^H s over the head rows (into piv-free scratch h below)
-  for (int j = tid; j < kG; j += kWG) {
-    cd c{0.0, 0.0};
-    for (int i = j; i < kG; ++i) c = cadd(c, cmul(ld2(tij(a.G.T, kmax, j, i)), h[i]));
-    st2(a.coef + a.cl.c2 + 2 * j, c);
+  {
+    double* coef = a.coef + a.cl.c2;
+    t_row_sums(
+        a.G.T, kmax, kG, [=](int i) { return h[i]; },
+        [=](int j, cd c) { st2(coef + 2 * j, c); }, lds);
+  }
+  {
+    const SideDev G = a.G;
+    const int f64 = a.f64;
+    col_dots(
+        kG, [](int j) { return j; }, [=](int) { return kG; },
+        [=](int i, int j) { return cjmul(uent(G, f64, i, j), h2[i]); },
+        [=](int j, cd v) { h[j] = v; });
   }
   __syncthreads();
-  for (int j = tid; j < kG; j += kWG) {
-    cd s{0.0, 0.0};
-    for (int i = j; i < kG; ++i) s = cadd(s, cjmul(uent(a.G, a.f64, i, j), h2[i]));
-    h[j] = s;
-  }
-  __syncthreads();
-  for (int j = tid; j < kG; j += kWG) {
-    cd c{0.0, 0.0};
-    for (int i = j; i < kG; ++i) c = cadd(c, cmul(ld2(tij(a.G.T, kmax, j, i)), h[i]));
-    st2(a.coef + a.cl.c3 + 2 * j, c);
+  {
+    double* coef = a.coef + a.cl.c3;
+    t_row_sums(
+        a.G.T, kmax, kG, [=](int i) { return h[i]; },
+        [=](int j, cd c) { st2(coef + 2 * j, c); }, lds);
   }
 }
 
