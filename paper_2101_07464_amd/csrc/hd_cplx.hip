@@ -705,11 +705,15 @@ __device__ __forceinline__ double* tij(double* T, int kmax, int i, int j) {
   return T + 2 * ((int64_t)i + (int64_t)j * kmax);
 }
 
-// Panel entry (row i, column j) of a side in its storage type.
+// Panel entry (row i, column j) of a side stored as T.
+template <typename T>
+__device__ __forceinline__ cd uent_t(const SideDev& S, int64_t i, int j) {
+  return ldc<T>((const T*)S.U + 2 * (int64_t)j * S.ld, i);
+}
+// The same in the side's storage type.
 __device__ __forceinline__ cd uent(const SideDev& S, int f64, int64_t i,
                                    int j) {
-  if (f64) return ldc<double>((const double*)S.U + 2 * (int64_t)j * S.ld, i);
-  return ldc<float>((const float*)S.U + 2 * (int64_t)j * S.ld, i);
+  return f64 ? uent_t<double>(S, i, j) : uent_t<float>(S, i, j);
 }
 __device__ __forceinline__ void uset(const SideDev& S, int f64, int64_t i,
                                      int j, cd v) {
@@ -757,14 +761,19 @@ __device__ void build_reflector(const SideDev& S, int f64, int k, double ss,
   st2(S.del + 2 * k, cmul(prev, c));
 }
 
+constexpr int kTriGroup = 8;  // loads in flight per lane in t_row_sums
+
 // out(j, s_j) for j < n with s_j = sum over i in [j, n) of T[j, i] v(i):
 // the row sums of the leading n x n block of a side's complex T factor
-// (column-major, leading dimension kmax).  The lanes take the rows and the
-// waves the columns in turn, so every load reads consecutive entries of one
-// column (a thread summing its own row would touch one cache line per
-// entry, in a serial chain); per block of 64 rows the waves' partial sums
-// are added in fixed order through `lds` (kWG entries).  Every thread of
-// the workgroup calls it; it ends with a barrier.
+// (column-major, leading dimension kmax, upper triangle set).  The lanes
+// take the rows and the waves the columns in turn, so every load reads
+// consecutive entries of one column (a thread summing its own row would
+// touch one cache line per entry, in a serial chain), and kTriGroup columns
+// are loaded before any is added: the indexes are clamped into the upper
+// triangle, so no load sits behind a branch (which would wait out each
+// load on its own); per block of 64 rows the waves' partial sums are added
+// in fixed order through `lds` (kWG entries).  Every thread of the
+// workgroup calls it; it ends with a barrier.
 template <typename V, typename Out>
 __device__ void t_row_sums(const double* __restrict__ T, int kmax, int n,
                            V v, Out out, cd* lds) {
@@ -772,9 +781,19 @@ __device__ void t_row_sums(const double* __restrict__ T, int kmax, int n,
   for (int r0 = 0; r0 < n; r0 += 64) {
     const int j = r0 + lane;
     cd s{0.0, 0.0};
-#pragma unroll 8
-    for (int i = r0 + wave; i < n; i += kWaves)
-      if (j <= i) s = cadd(s, cmul(ld2(tij((double*)T, kmax, j, i)), v(i)));
+    for (int i0 = r0 + wave; i0 < n; i0 += kWaves * kTriGroup) {
+      cd t[kTriGroup];
+#pragma unroll
+      for (int u = 0; u < kTriGroup; ++u) {
+        const int i = min(i0 + u * kWaves, n - 1);
+        t[u] = cmul(ld2(tij((double*)T, kmax, min(j, i), i)), v(i));
+      }
+#pragma unroll
+      for (int u = 0; u < kTriGroup; ++u) {
+        const int i = i0 + u * kWaves;
+        if (i < n && j <= i) s = cadd(s, t[u]);
+      }
+    }
     lds[tid] = s;
     __syncthreads();
     if (wave == 0 && j < n) {
@@ -787,21 +806,43 @@ __device__ void t_row_sums(const double* __restrict__ T, int kmax, int n,
 }
 
 // out(j, s_j) for j < nc with s_j = sum over i in [lo(j), hi(j)) of
-// f(i, j), where f reads column j of a column-major factor (a panel or T):
-// the waves take the columns in turn and the lanes the rows, so each load
-// reads consecutive entries of one column, and a butterfly over the wave
-// adds the lanes' terms.  Every thread of the workgroup calls it; no
-// barrier.
-template <typename Lo, typename Hi, typename F, typename Out>
+// f(i, j), where f reads column j of a column-major factor (a panel or T),
+// lo, hi never decrease with j and lo(j) < hi(j).  Each wave takes CG
+// consecutive columns at a time and the lanes the rows, 64 at a time: a
+// load reads consecutive entries of one column, and the CG loads of a lane
+// are all issued before any is added (one column at a time would wait out
+// a memory round trip per 64 rows of every column); f is called with
+// indexes clamped into the column, so that no load sits behind a branch.
+// A butterfly over the wave adds the lanes' terms of each column.  Every
+// thread of the workgroup calls it; no barrier.
+template <int CG, typename Lo, typename Hi, typename F, typename Out>
 __device__ void col_dots(int nc, Lo lo, Hi hi, F f, Out out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < nc; j += kWaves) {
-    cd s{0.0, 0.0};
-    const int e = hi(j);
-    for (int i = lo(j) + lane; i < e; i += 64) s = cadd(s, f(i, j));
-    s.re = wave_sum(s.re);
-    s.im = wave_sum(s.im);
-    if (lane == 0) out(j, s);
+  for (int jb = wave * CG; jb < nc; jb += kWaves * CG) {
+    const int jl = min(jb + CG, nc) - 1;
+    const int r1 = hi(jl);
+    cd s[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) s[c] = {0.0, 0.0};
+    for (int r = lo(jb); r < r1; r += 64) {
+      const int i = r + lane;
+      cd v[CG];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        const int j = min(jb + c, jl);
+        v[c] = f(min(max(i, lo(j)), hi(j) - 1), j);
+      }
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        const int j = jb + c;
+        if (j <= jl && i >= lo(j) && i < hi(j)) s[c] = cadd(s[c], v[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      const double re = wave_sum(s[c].re), im = wave_sum(s[c].im);
+      if (lane == 0 && jb + c <= jl) out(jb + c, cd{re, im});
+    }
   }
 }
 
@@ -818,6 +859,7 @@ __device__ void t_column(const SideDev& S, int kmax, int k, const cd* h,
 }
 
 constexpr int kSmallMax = kMaxT + 1;
+constexpr int kColGroup = 8;  // columns per wave in col_dots
 
 // PH 0: z = T_D^H w.  PH 1: Haar S2.  PH 2: Ginibre S2.
 template <int PH>
@@ -843,7 +885,7 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
     double* T = a.D.T;
     const double* w = a.red + a.rl.w;
     double* z = a.coef + a.cl.z;
-    col_dots(
+    col_dots<kColGroup>(
         a.kD, [](int) { return 0; }, [](int j) { return j + 1; },
         [=](int i, int j) { return cjmul(ld2(tij(T, kmax, i, j)), ld2(w + 2 * i)); },
         [=](int j, cd v) { st2(z + 2 * j, v); });
@@ -888,14 +930,21 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
     // h2_j = sum over i in [j, k] of conj(U_G[i, j]) s_i (the new pivot
     // entry in FP64)
     const SideDev G = a.G;
-    const int f64 = a.f64;
     const cd pk = piv[1];
-    col_dots(
-        k + 1, [](int j) { return j; }, [=](int) { return k + 1; },
-        [=](int i, int j) {
-          return cjmul(i == k && j == k ? pk : uent(G, f64, i, j), h[i]);
-        },
-        [=](int j, cd v) { h2[j] = v; });
+    auto dots = [&](auto tag) {
+      using T = decltype(tag);
+      col_dots<kColGroup>(
+          k + 1, [](int j) { return j; }, [=](int) { return k + 1; },
+          [=](int i, int j) {
+            const cd u = uent_t<T>(G, i, j);
+            return cjmul(i == k && j == k ? pk : u, h[i]);
+          },
+          [=](int j, cd v) { h2[j] = v; });
+    };
+    if (a.f64)
+      dots(double{});
+    else
+      dots(float{});
     __syncthreads();
     double* coef = a.coef + a.cl.c1;
     t_row_sums(
@@ -928,11 +977,17 @@ __global__ __launch_bounds__(kWG) void k_cx_small(SmallArgs a) {
   }
   {
     const SideDev G = a.G;
-    const int f64 = a.f64;
-    col_dots(
-        kG, [](int j) { return j; }, [=](int) { return kG; },
-        [=](int i, int j) { return cjmul(uent(G, f64, i, j), h2[i]); },
-        [=](int j, cd v) { h[j] = v; });
+    auto dots = [&](auto tag) {
+      using T = decltype(tag);
+      col_dots<kColGroup>(
+          kG, [](int j) { return j; }, [=](int) { return kG; },
+          [=](int i, int j) { return cjmul(uent_t<T>(G, i, j), h2[i]); },
+          [=](int j, cd v) { h[j] = v; });
+    };
+    if (a.f64)
+      dots(double{});
+    else
+      dots(float{});
   }
   __syncthreads();
   {
