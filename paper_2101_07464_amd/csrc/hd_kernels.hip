@@ -385,9 +385,13 @@ __device__ __forceinline__ void wg_sums(int nout, Lo lo, Hi hi, Term term,
 // dimension tm) against one or two coefficient vectors.  The lanes take the
 // rows and the waves the columns in turn, so every load reads consecutive
 // entries of one column (reading T by rows would touch one cache line per
-// entry); per block of 64 rows the waves' partial sums are added in fixed
-// order through LDS.  Every thread of the workgroup calls it; `lds` holds
-// 2 * kWG doubles.  Ends with a barrier.
+// entry).  kTriGroup columns are loaded before any is added, at indexes
+// clamped into the triangle: a load behind the j <= l branch would wait out
+// its own round trip before the next one is issued.  Per block of 64 rows
+// the waves' partial sums are added in fixed order through LDS.  Every
+// thread of the workgroup calls it; `lds` holds 2 * kWG doubles.  Ends with
+// a barrier.
+constexpr int kTriGroup = 8;
 template <int NT, typename C0, typename C1, typename Out>
 __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
                                              int tm, int n, C0 coef0,
@@ -396,13 +400,22 @@ __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
   for (int r0 = 0; r0 < n; r0 += 64) {
     const int j = r0 + lane;
     double s0 = 0.0, s1 = 0.0;
-    // unrolled so that many columns' loads are in flight at once
-#pragma unroll 16
-    for (int l = r0 + wave; l < n; l += kWaves) {
-      if (j <= l) {
-        const double t = T[j + (int64_t)l * tm];
-        s0 += t * coef0(l);
-        if (NT == 2) s1 += t * coef1(l);
+    for (int l0 = r0 + wave; l0 < n; l0 += kWaves * kTriGroup) {
+      double t[kTriGroup], c0[kTriGroup], c1[kTriGroup];
+#pragma unroll
+      for (int u = 0; u < kTriGroup; ++u) {
+        const int l = min(l0 + u * kWaves, n - 1);
+        t[u] = T[min(j, l) + (int64_t)l * tm];
+        c0[u] = coef0(l);
+        c1[u] = NT == 2 ? coef1(l) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kTriGroup; ++u) {
+        const int l = l0 + u * kWaves;
+        if (l < n && j <= l) {
+          s0 += t[u] * c0[u];
+          if (NT == 2) s1 += t[u] * c1[u];
+        }
       }
     }
     lds[tid] = s0;
