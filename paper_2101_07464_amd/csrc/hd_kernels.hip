@@ -379,6 +379,74 @@ __device__ __forceinline__ void wg_sums(int nout, Lo lo, Hi hi, Term term,
   }
 }
 
+// out(j, s_j) for j < nout with s_j = sum over i in [lo(j), hi(j)) of
+// term(i, j), where term reads column j of a column-major matrix (a panel
+// head or T), lo and hi never decrease with j, and lo(j) < hi(j).  Each wave
+// takes kColGroup consecutive outputs at a time and its lanes the rows, 64
+// at a time, so that a load reads consecutive entries of one column (one
+// thread per output would read its column alone, every lane of a load in
+// another column: a cache line, and for the panels a page, per lane); the
+// loads of a group are all issued before any is added, at indexes clamped
+// into the column, and a butterfly over the wave adds the lanes' terms.
+// Every thread of the workgroup calls it; ends with a barrier.
+constexpr int kColGroup = 8;
+template <typename Lo, typename Hi, typename Term, typename Out>
+__device__ __forceinline__ void col_sums(int nout, Lo lo, Hi hi, Term term,
+                                         Out out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int jb = wave * kColGroup; jb < nout; jb += kWaves * kColGroup) {
+    const int jl = min(jb + kColGroup, nout) - 1;
+    const int r1 = hi(jl);
+    double s[kColGroup];
+#pragma unroll
+    for (int c = 0; c < kColGroup; ++c) s[c] = 0.0;
+    for (int r = lo(jb); r < r1; r += 64) {
+      const int i = r + lane;
+      double v[kColGroup];
+#pragma unroll
+      for (int c = 0; c < kColGroup; ++c) {
+        const int j = min(jb + c, jl);
+        v[c] = term(min(max(i, lo(j)), hi(j) - 1), j);
+      }
+#pragma unroll
+      for (int c = 0; c < kColGroup; ++c) {
+        const int j = jb + c;
+        if (j <= jl && i >= lo(j) && i < hi(j)) s[c] += v[c];
+      }
+    }
+    // every lane holds every sum after the butterfly: lane c writes output
+    // jb + c, so that the loads out() may make are issued together
+    double mine = 0.0;
+#pragma unroll
+    for (int c = 0; c < kColGroup; ++c) {
+      const double t = wave_sum(s[c]);
+      if (lane == c) mine = t;
+    }
+    if (lane < kColGroup && jb + lane <= jl) out(jb + lane, mine);
+  }
+  __syncthreads();
+}
+
+// The column sums of a small step: by col_sums in the single-trial kernels
+// (one workgroup, latency-bound, COLS), by wg_sums in the batched ones,
+// where thousands of workgroups run side by side and the butterflies'
+// arithmetic costs more than it hides.
+template <bool COLS, typename Lo, typename Hi, typename Term, typename Out>
+__device__ __forceinline__ void head_sums(int nout, Lo lo, Hi hi, Term term,
+                                          Out out, double* lds) {
+  if constexpr (COLS) {
+    col_sums(nout, lo, hi, term, out);
+  } else {
+    wg_sums<1>(
+        nout, lo, hi,
+        [=](int i, int j, double& t0, double& t1) {
+          t0 = term(i, j);
+          t1 = 0.0;
+        },
+        [=](int j, double v, double) { out(j, v); }, lds);
+  }
+}
+
 // out(j, s0_j, s1_j) for j < n with s_r,j = sum over l in [j, n) of
 // T[j, l] coef_r(l) (coef_1 only when NT = 2): the row sums of the leading
 // n x n block of an upper-triangular factor T (column-major, leading
@@ -435,6 +503,7 @@ __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
 
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
 // Schreiber and Van Loan), then z = T' w for the leading k x k block.
+template <bool COLS = false>
 __device__ void small_data_body(const SmallDataArgs& a) {
   __shared__ double lds[2 * kWG];
   const int tm = a.tmax, kp = a.kp;
@@ -451,13 +520,10 @@ __device__ void small_data_body(const SmallDataArgs& a) {
   if (a.w) {
     const double* w = a.w;
     double* z = a.z;
-    wg_sums<1>(
+    head_sums<COLS>(
         a.k, [](int) { return 0; }, [](int j) { return j + 1; },
-        [=](int i, int j, double& t0, double& t1) {
-          t0 = Tm[i + (int64_t)j * tm] * w[i];
-          t1 = 0.0;
-        },
-        [=](int j, double r0, double) { z[j] = r0; }, lds);
+        [=](int i, int j) { return Tm[i + (int64_t)j * tm] * w[i]; },
+        [=](int j, double r0) { z[j] = r0; }, lds);
   }
 }
 
@@ -514,7 +580,7 @@ __device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
 // over rows > k and ||g[k+1:]||^2, its T column, s_vec = V' Delta w for
 // w = [p[:k]; (nu/||g[k:]||) g[k:]] (the vector L_t R_t p_t of eq. (Qtxt)
 // before L_1..L_{t-1}), and z_G = T_G s_vec.
-template <typename T>
+template <typename T, bool COLS = false>
 __device__ void haar_small_body(const HaarSmallArgs& a) {
   __shared__ double sh[6];
   __shared__ double lds[2 * kWG];
@@ -561,13 +627,12 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
   const double* __restrict__ gdot = a.G.red;
   // hg_j = sum_{j <= i < k} V_G[i, j] pi_{i+1} head_i; then the dots of the
   // new random reflector (cG) and s_vec (sv)
-  wg_sums<1>(
+  head_sums<COLS>(
       k, [](int j) { return j; }, [k](int) { return k; },
-      [=](int i, int j, double& t0, double& t1) {
-        t0 = (double)VGr[(int64_t)j * ldG + i] * piG[i + 1] * head[i];
-        t1 = 0.0;
+      [=](int i, int j) {
+        return (double)VGr[(int64_t)j * ldG + i] * piG[i + 1] * head[i];
       },
-      [=](int j, double hg, double) {
+      [=](int j, double hg) {
         const double vk = (double)VGr[(int64_t)j * ldG + k];
         cG[j] = gdot[j] + vk * upG;
         sv[j] = hg + piGk * cs * (gdot[j] + vk * gk);
@@ -590,7 +655,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
 // Ginibre: the data reflector, then the random-side coefficients
 // s1 = V_G' Delta_G [0; g] = pi_l (prefetched dots over rows >= l),
 // s2 = V_G' Delta_G h (head rows only) + nu s1; z1 = T_G s1, z2 = T_G s2.
-template <typename T>
+template <typename T, bool COLS = false>
 __device__ void gin_small_body(const GinSmallArgs& a) {
   __shared__ double sh[3];
   __shared__ double lds[2 * kWG];
@@ -612,13 +677,12 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   const double* __restrict__ piG = a.G.pi;
   const double* __restrict__ h = a.h;
   const double* __restrict__ gdot = a.G.red;
-  wg_sums<1>(
+  head_sums<COLS>(
       l, [](int j) { return j; }, [l](int) { return l; },
-      [=](int i, int j, double& t0, double& t1) {
-        t0 = (double)VG[(int64_t)j * ldG + i] * piG[i + 1] * h[i];
-        t1 = 0.0;
+      [=](int i, int j) {
+        return (double)VG[(int64_t)j * ldG + i] * piG[i + 1] * h[i];
       },
-      [=](int j, double hs, double) {
+      [=](int j, double hs) {
         const double v1 = pil * gdot[j];
         s1[j] = v1;
         s2[j] = hs + nu * v1;
@@ -1565,17 +1629,17 @@ __global__ __launch_bounds__(kWG) void k_reduce2(ReduceJob ja, ReduceJob jb) {
 }
 
 __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
-  small_data_body(a);
+  small_data_body<true>(a);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_haar_small(HaarSmallArgs a) {
-  haar_small_body<T>(a);
+  haar_small_body<T, true>(a);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_gin_small(GinSmallArgs a) {
-  gin_small_body<T>(a);
+  gin_small_body<T, true>(a);
 }
 
 template <typename T>
