@@ -427,10 +427,11 @@ __device__ __forceinline__ void col_sums(int nout, Lo lo, Hi hi, Term term,
   __syncthreads();
 }
 
-// The column sums of a small step: by col_sums in the single-trial kernels
-// (one workgroup, latency-bound, COLS), by wg_sums in the batched ones,
-// where thousands of workgroups run side by side and the butterflies'
-// arithmetic costs more than it hides.
+// The column sums of a small step: by col_sums where they read the panel
+// head in a single-trial kernel (one workgroup, latency-bound, COLS), by
+// wg_sums in the batched ones, where thousands of workgroups run side by
+// side and the butterflies' arithmetic costs more than it hides, and for
+// z = T'w, whose T factor is small and stays cached.
 template <bool COLS, typename Lo, typename Hi, typename Term, typename Out>
 __device__ __forceinline__ void head_sums(int nout, Lo lo, Hi hi, Term term,
                                           Out out, double* lds) {
@@ -1629,7 +1630,7 @@ __global__ __launch_bounds__(kWG) void k_reduce2(ReduceJob ja, ReduceJob jb) {
 }
 
 __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
-  small_data_body<true>(a);
+  small_data_body<false>(a);  // T is small and cached: the strided sums win
 }
 
 template <typename T>
