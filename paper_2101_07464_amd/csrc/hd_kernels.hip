@@ -454,14 +454,17 @@ __device__ __forceinline__ void head_sums(int nout, Lo lo, Hi hi, Term term,
 // dimension tm) against one or two coefficient vectors.  The lanes take the
 // rows and the waves the columns in turn, so every load reads consecutive
 // entries of one column (reading T by rows would touch one cache line per
-// entry).  kTriGroup columns are loaded before any is added, at indexes
-// clamped into the triangle: a load behind the j <= l branch would wait out
-// its own round trip before the next one is issued.  Per block of 64 rows
+// entry).  With GRP (the single-trial kernels, latency-bound) kTriGroup
+// columns are loaded before any is added, at indexes clamped into the
+// triangle: a load behind the j <= l branch would wait out its own round
+// trip before the next one is issued.  The batched kernels, thousands of
+// workgroups side by side, keep the plain loop, whose skipped entries cost
+// nothing there and whose latency the other workgroups hide.  Per block of 64 rows
 // the waves' partial sums are added in fixed order through LDS.  Every
 // thread of the workgroup calls it; `lds` holds 2 * kWG doubles.  Ends with
 // a barrier.
 constexpr int kTriGroup = 8;
-template <int NT, typename C0, typename C1, typename Out>
+template <int NT, bool GRP, typename C0, typename C1, typename Out>
 __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
                                              int tm, int n, C0 coef0,
                                              C1 coef1, Out out, double* lds) {
@@ -469,21 +472,32 @@ __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
   for (int r0 = 0; r0 < n; r0 += 64) {
     const int j = r0 + lane;
     double s0 = 0.0, s1 = 0.0;
-    for (int l0 = r0 + wave; l0 < n; l0 += kWaves * kTriGroup) {
-      double t[kTriGroup], c0[kTriGroup], c1[kTriGroup];
-#pragma unroll
-      for (int u = 0; u < kTriGroup; ++u) {
-        const int l = min(l0 + u * kWaves, n - 1);
-        t[u] = T[min(j, l) + (int64_t)l * tm];
-        c0[u] = coef0(l);
-        c1[u] = NT == 2 ? coef1(l) : 0.0;
+    if constexpr (!GRP) {
+#pragma unroll 16
+      for (int l = r0 + wave; l < n; l += kWaves) {
+        if (j <= l) {
+          const double t = T[j + (int64_t)l * tm];
+          s0 += t * coef0(l);
+          if (NT == 2) s1 += t * coef1(l);
+        }
       }
+    } else {
+      for (int l0 = r0 + wave; l0 < n; l0 += kWaves * kTriGroup) {
+        double t[kTriGroup], c0[kTriGroup], c1[kTriGroup];
 #pragma unroll
-      for (int u = 0; u < kTriGroup; ++u) {
-        const int l = l0 + u * kWaves;
-        if (l < n && j <= l) {
-          s0 += t[u] * c0[u];
-          if (NT == 2) s1 += t[u] * c1[u];
+        for (int u = 0; u < kTriGroup; ++u) {
+          const int l = min(l0 + u * kWaves, n - 1);
+          t[u] = T[min(j, l) + (int64_t)l * tm];
+          c0[u] = coef0(l);
+          c1[u] = NT == 2 ? coef1(l) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kTriGroup; ++u) {
+          const int l = l0 + u * kWaves;
+          if (l < n && j <= l) {
+            s0 += t[u] * c0[u];
+            if (NT == 2) s1 += t[u] * c1[u];
+          }
         }
       }
     }
@@ -504,7 +518,7 @@ __device__ __forceinline__ void tri_row_sums(const double* __restrict__ T,
 
 // Column kp of T from the dots c = V[:, :kp]' u_kp (compact-WY recurrence of
 // Schreiber and Van Loan), then z = T' w for the leading k x k block.
-template <bool COLS = false>
+template <bool COLS = false, bool GRP = false>
 __device__ void small_data_body(const SmallDataArgs& a) {
   __shared__ double lds[2 * kWG];
   const int tm = a.tmax, kp = a.kp;
@@ -513,7 +527,7 @@ __device__ void small_data_body(const SmallDataArgs& a) {
     const double tau = a.tau[kp];
     const double* c = a.c;
     double* Tw = a.T;
-    tri_row_sums<1>(
+    tri_row_sums<1, GRP>(
         Tm, tm, kp, [=](int l) { return c[l]; }, [](int) { return 0.0; },
         [=](int j, double r0, double) { Tw[j + (int64_t)kp * tm] = -tau * r0; },
         lds);
@@ -561,14 +575,14 @@ __device__ double data_reflector(const PanelDev& D, int k, int tm, double ss,
 // columns with the stored rows > k of u_k, summed by the data pass, plus the
 // pivot row (V[k, j] * u_k[k]): T[:k, k] = -tau_k T[:k, :k] c.  Every thread
 // of the workgroup calls it.
-template <typename T>
+template <typename T, bool GRP = false>
 __device__ void data_tcol(const PanelDev& D, int k, int tm, double up,
                           double tau, const double* c, double* lds) {
   const T* __restrict__ V = (const T*)D.V;
   const double* __restrict__ Tm = D.T;
   double* Tw = D.T;
   const int64_t ld = D.ld;
-  tri_row_sums<1>(
+  tri_row_sums<1, GRP>(
       Tm, tm, k,
       [=](int l) { return c[l] + (double)V[(int64_t)l * ld + k] * up; },
       [](int) { return 0.0; },
@@ -642,7 +656,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
   const double* __restrict__ TG = a.G.T;
   double* TGw = a.G.T;
   double* zG = a.zG;
-  tri_row_sums<2>(
+  tri_row_sums<2, COLS>(
       TG, tm, k, [=](int l) { return sv[l]; }, [=](int l) { return cG[l]; },
       [=](int j, double zz, double tg) {
         zG[j] = zz;
@@ -650,7 +664,7 @@ __device__ void haar_small_body(const HaarSmallArgs& a) {
       },
       lds);
   if (a.cslot >= 0)
-    data_tcol<T>(a.D, k, tm, sh[4], sh[5], a.D.red + a.cslot, lds);
+    data_tcol<T, COLS>(a.D, k, tm, sh[4], sh[5], a.D.red + a.cslot, lds);
 }
 
 // Ginibre: the data reflector, then the random-side coefficients
@@ -692,7 +706,7 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
   const double* __restrict__ TG = a.G.T;
   double* z1 = a.z1;
   double* z2 = a.z2;
-  tri_row_sums<2>(
+  tri_row_sums<2, COLS>(
       TG, tm, l, [=](int q) { return s1[q]; }, [=](int q) { return s2[q]; },
       [=](int j, double r0, double r1) {
         z1[j] = r0;
@@ -700,7 +714,7 @@ __device__ void gin_small_body(const GinSmallArgs& a) {
       },
       lds);
   if (a.cslot >= 0)
-    data_tcol<T>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot, lds);
+    data_tcol<T, COLS>(a.D, k, tm, sh[1], sh[2], a.D.red + a.cslot, lds);
 }
 
 __device__ __forceinline__ double soft(double v, double th) {
@@ -844,7 +858,7 @@ __device__ __forceinline__ void tdot_body(const TdotArgs& a, int blk) {
 
 // ---------------------------------------------------------------- GEMV-N --
 
-template <typename T, int CPT, int MODE, bool DB = false>
+template <typename T, int CPT, int MODE, bool DB = false, bool GRP = false>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
   __shared__ double gpf[CPT * kChunkRows];   // next draw (prefetch)
   __shared__ double gcur[CPT * kChunkRows];  // this draw, or the new column
@@ -882,7 +896,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
       const bool first = blk == 0;
       if (kp > 0) {
         const double tau = a.tau[kp];
-        tri_row_sums<1>(
+        tri_row_sums<1, GRP>(
             Tm, tm, kp, [=](int l) { return cc[l]; }, [](int) { return 0.0; },
             [=](int j, double r0, double) {
               tc[j] = -tau * r0;
@@ -998,7 +1012,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int blk) {
 
 // ------------------------------------------------- Ginibre random side --
 
-template <typename T, int CPT, bool DB = false>
+template <typename T, int CPT, bool DB = false, bool GRP = false>
 __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
   __shared__ double gpf[CPT * kChunkRows];
   __shared__ double gcur[CPT * kChunkRows];
@@ -1060,7 +1074,7 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
           },
           comb);
       const double* __restrict__ TG = g.G.T;
-      tri_row_sums<2>(
+      tri_row_sums<2, GRP>(
           TG, tm, l, [=](int q) { return s1l[q]; },
           [=](int q) { return s2l[q]; },
           [=](int j, double r0, double r1) {
@@ -1071,7 +1085,7 @@ __device__ __forceinline__ void gin_pass_body(const GinPassArgs& a, int blk) {
       z1 = z1l;
       z2 = z2l;
       if (blk == 0 && g.cslot >= 0)
-        data_tcol<T>(g.D, kD, tm, shr[1], shr[2], g.D.red + g.cslot, comb);
+        data_tcol<T, GRP>(g.D, kD, tm, shr[1], shr[2], g.D.red + g.cslot, comb);
     }
   }
   // reflector panel: acc0 -= V z1 (new basis vector), acc1 -= V z2 (output),
@@ -1142,12 +1156,12 @@ __global__ __launch_bounds__(kWG) void k_tdot(TdotArgs a) {
 
 template <typename T, int CPT, int MODE, bool DB = false>
 __global__ __launch_bounds__(kWG) void k_pass(PassArgs a) {
-  pass_body<T, CPT, MODE, DB>(a, blockIdx.x);
+  pass_body<T, CPT, MODE, DB, true>(a, blockIdx.x);
 }
 
 template <typename T, int CPT, bool DB = false>
 __global__ __launch_bounds__(kWG) void k_gin_pass(GinPassArgs a) {
-  gin_pass_body<T, CPT, DB>(a, blockIdx.x);
+  gin_pass_body<T, CPT, DB, true>(a, blockIdx.x);
 }
 
 // --------------------------------------------------- ISTA layer adjoint --
@@ -1630,7 +1644,7 @@ __global__ __launch_bounds__(kWG) void k_reduce2(ReduceJob ja, ReduceJob jb) {
 }
 
 __global__ __launch_bounds__(kWG) void k_small_data(SmallDataArgs a) {
-  small_data_body<false>(a);  // T is small and cached: the strided sums win
+  small_data_body<false, true>(a);  // z = T'w: strided sums (T is cached)
 }
 
 template <typename T>
